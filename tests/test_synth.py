@@ -1,0 +1,74 @@
+"""The seeded input generator (CPU only)."""
+import numpy as np
+import torch
+
+from oracle import geometry
+from paper_1401_7494_amd import synth
+
+
+def test_phantom_is_seeded():
+    a = synth.random_ellipsoids(1402)
+    b = synth.random_ellipsoids(1402)
+    c = synth.random_ellipsoids(1403)
+    assert np.array_equal(a.centres, b.centres) and np.array_equal(a.densities, b.densities)
+    assert not np.array_equal(a.centres, c.centres)
+    assert (np.linalg.norm(a.centres, axis=1) <= 70.0).all()
+    assert ((a.axes >= 10) & (a.axes <= 60)).all()
+    R = a.rotations
+    assert np.allclose(np.einsum("nij,nkj->nik", R, R), np.eye(3), atol=1e-12)
+
+
+def test_sphere_chord_lengths():
+    """A centred sphere of radius R: the central ray's integral is 2R, a ray at offset h gives 2 sqrt(R^2 - h'^2)."""
+    R = 50.0
+    sph = synth.Ellipsoids(np.zeros((1, 3)), np.full((1, 3), R), np.eye(3)[None], np.array([1.0]))
+    sc = synth.Scanner(n_views=1, W=65, H=33, pitch=1.0)
+    p = synth.line_integrals(sc, sph, [0]).numpy()[0]
+    assert abs(p[16, 32] - 2 * R) < 1e-9
+    # pixel 20 columns right of centre: the ray passes the centre at distance d*SID/sqrt(SDD^2 + 20^2)
+    off = 20.0
+    h = sc.sid * off / np.hypot(sc.sdd, off)
+    assert abs(p[16, 32 + 20] - 2 * np.sqrt(R * R - h * h)) < 1e-9
+
+
+def test_ramp_kernel_has_zero_dc():
+    h = synth.ramp_kernel(1 << 16, 0.2)
+    assert abs(float(h.sum())) < 1e-4 * float(h[0])
+
+
+def test_projection_lands_where_the_matrix_says():
+    """A small ball at X0 projects to a blob centred (first moment) at the matrix image of X0."""
+    X0 = np.array([30.0, -20.0, 15.0])
+    ball = synth.Ellipsoids(X0[None], np.full((1, 3), 3.0), np.eye(3)[None], np.array([1.0]))
+    sc = synth.Scanner(n_views=3, W=400, H=120, pitch=0.5)
+    p = synth.line_integrals(sc, ball, range(3)).numpy()
+    P = geometry.circular_matrices(*sc.geometry_args())
+    s, t, _ = geometry.apply(P, X0[None])
+    j, i = np.mgrid[0:sc.H, 0:sc.W]
+    for k in range(3):
+        m = p[k].sum()
+        ci, cj = (p[k] * i).sum() / m, (p[k] * j).sum() / m
+        assert abs(ci - s[k, 0]) < 0.05 and abs(cj - t[k, 0]) < 0.05
+
+
+def test_filtered_projections_shapes_and_dtypes():
+    sc = synth.Scanner(n_views=3, W=40, H=24, pitch=6.0)
+    ph = synth.random_ellipsoids(7)
+    f32 = synth.filtered_projections(sc, ph)
+    f16 = synth.filtered_projections(sc, ph, out_dtype=torch.float16)
+    bf = synth.filtered_projections(sc, ph, out_dtype=torch.bfloat16)
+    assert f32.shape == (3, 24, 40) and f32.dtype == torch.float32
+    assert torch.equal(f16, f32.to(torch.float16))
+    assert f32.abs().max() > 0 and (f32 < 0).any()  # filtered: signed
+    assert bf.dtype == torch.bfloat16
+    noisy = synth.filtered_projections(sc, ph, noise_frac=0.01, noise_seed=1)
+    again = synth.filtered_projections(sc, ph, noise_frac=0.01, noise_seed=1)
+    assert torch.equal(noisy, again) and not torch.equal(noisy, f32)
+
+
+def test_poisson_stream_is_seeded():
+    a = synth.poisson_requests(20, 5.0, 1405)
+    b = synth.poisson_requests(20, 5.0, 1405)
+    assert [r.arrival_s for r in a] == [r.arrival_s for r in b]
+    assert all(x.arrival_s <= y.arrival_s for x, y in zip(a, a[1:]))
+    assert {r.L for r in a} <= {128, 256, 512}

@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the HIP back projector on one MI355X.
+
+Workload: L=512 volume (512^3 FP32, voxel 0.5 mm, centred), 496 filtered
+projections of 1248 x 960 from a seeded random-ellipsoid phantom on a 200
+degree circular orbit (SID 800 mm, SDD 1200 mm, pitch 0.32 mm).  A step is
+one full reconstruction: all 496 views back projected into the volume
+(per-view constants, zero-padded staging and the back-projection passes),
+inputs resident in HBM.  GUPS = L^3 * views / step time.
+
+Forms timed on the same GPU and inputs:
+  fused_f32    K views per volume pass, FP32 projections (the headline `value`)
+  plain_f32    one volume pass per view (the paper's one-call-per-projection form)
+  fused_bf16   fused, projections stored as BF16 (FP32 interpolation and accumulation)
+  fused_f16    fused, projections stored as FP16
+
+Prints one JSON line.  Each form's error is stated against the FP64 oracle on
+the FP32 data over the centre 128^3 block (the CPU-baseline sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PER_UPDATE = 22  # minimal VALU instructions per voxel update of the fused form
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes/clk x 2.4 GHz, lane-instructions/s (no packed FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--forms", default="fused_f32,plain_f32,fused_bf16,fused_f16")
+    ap.add_argument("--workload", default="fdk_l512_v496_f32")
+    ap.add_argument("--k", type=int, default=0, help="views per pass for fused forms (0 = tuned)")
+    ap.add_argument("--zu", type=int, default=0, help="z-unroll (0 = tuned)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-block", type=int, default=128, help="edge of the centre block the oracle times")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu):
+    path, dt = form.split("_")
+    proj = proj_by_dtype[dt]
+    n, H, W = proj.shape
+    L = vol_cfg.L
+    dev = proj.device
+    vol = torch.zeros((L, L, L), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = bp.Context(W, H, dt)
+    ctx.set_tuning(path, k, zu)
+    plan = ctx.plan(L, L, L, n)
+    for _ in range(warmup):
+        ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
+    torch.cuda.synchronize()
+    vol.zero_()
+    ctx.enable_timing(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    kern = {kind: ctx.kernel_timing(kind) for kind in ("backproject", "pad", "views")}
+    ctx.enable_timing(False)
+    ctx.close()
+    out = vol / float(steps)  # every step added the same reconstruction
+    return {
+        "path": plan.path, "dtype": dt, "views_per_pass": plan.views_per_pass, "z_unroll": plan.z_unroll,
+        "step_ms": step_ms, "wall_s": wall, "kernels": kern, "volume": out,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the z-slab sharding across GPUs "
+              "is a design in DESIGN.md, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1401_7494_amd import bp, synth
+
+    wl = synth.WORKLOADS[args.workload]
+    v = wl.volume
+    sc = wl.scanner
+    dev = torch.device("cuda:0")
+    log(f"bench: workload {wl.name} L={v.L} views={sc.n_views} det={sc.W}x{sc.H} on {torch.cuda.get_device_name(0)}")
+    t = time.perf_counter()
+    proj32 = synth.filtered_projections(sc, synth.random_ellipsoids(wl.phantom_seed), device=dev)
+    torch.cuda.synchronize()
+    log(f"bench: inputs generated on the GPU in {time.perf_counter() - t:.1f} s")
+    forms = [f for f in args.forms.split(",") if f]
+    proj_by_dtype = {"f32": proj32}
+    if any(f.endswith("bf16") for f in forms):
+        proj_by_dtype["bf16"] = proj32.to(torch.bfloat16)
+    if any(f.endswith("f16") and not f.endswith("bf16") for f in forms):
+        proj_by_dtype["f16"] = proj32.to(torch.float16)
+    _, P32 = bp.circular_matrices(*sc.geometry_args())
+    P = torch.from_numpy(P32).to(dev)
+
+    updates = float(v.L) ** 3 * sc.n_views
+    results = {}
+    for form in forms:
+        r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu)
+        ms = r["step_ms"]
+        r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
+        r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9
+        r["gups_p99"] = updates / (np.percentile(ms, 99) * 1e-3) / 1e9
+        log(f"bench: {form}: {ms.mean():.2f} ms/step  p50 {r['gups_p50']:.1f} GUPS  p99 {r['gups_p99']:.1f} GUPS  "
+            f"(path {r['path']} K={r['views_per_pass']} ZU={r['z_unroll']}) kernels {r['kernels']}")
+        results[form] = r
+
+    # CPU baseline: the oracle on the centre block, on this host's cores.
+    cpu = None
+    errors = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.bp import default_threads
+
+        b = args.cpu_block
+        lo = (v.L - b) // 2
+        blk = ((lo, lo + b),) * 3
+        proj_np = proj32.cpu().numpy()
+        P_or = oracle.geometry.circular_matrices(*sc.geometry_args()).astype(np.float32).astype(np.float64)
+        thr = default_threads()
+        t = time.perf_counter()
+        ref = oracle.backproject(proj_np, P_or, v.L, v.voxel_size, v.origin, block=blk, threads=thr)
+        dt = time.perf_counter() - t
+        n_upd = float(b) ** 3 * sc.n_views
+        cpu = {"value": round(n_upd / dt / 1e9, 4), "unit": "GUPS", "cores": thr, "kind": "oracle",
+               "sample": f"centre {b}^3 block of the {v.L}^3 volume x {sc.n_views} views "
+                         f"({n_upd:.3g} voxel updates, FP64, {dt:.1f} s)"}
+        log(f"bench: oracle {cpu}")
+        for form, r in results.items():
+            got = r["volume"][lo:lo + b, lo:lo + b, lo:lo + b].double().cpu().numpy()
+            d = got - ref
+            errors[form] = {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                            "max_abs_over_max": float(np.abs(d).max() / np.abs(ref).max()),
+                            "rms": float(np.sqrt(np.mean(d * d)))}
+
+    head = results.get("fused_f32") or next(iter(results.values()))
+    ms_bp, n_bp = head["kernels"]["backproject"]
+    per_launch_ms = ms_bp / max(n_bp, 1)
+    updates_per_launch = updates * args.steps / max(n_bp, 1)
+    achieved = updates_per_launch * VALU_PER_UPDATE / (per_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_T, 3),
+                "unit": "Tinstr/s", "frac": round(achieved / VALU_PEAK_T, 4), "traffic": None,
+                "kernel": "backproject_kernel", "avg_launch_ms": round(per_launch_ms, 4),
+                "updates_per_launch": updates_per_launch, "valu_instr_per_update": VALU_PER_UPDATE}
+
+    forms_out = {}
+    for form, r in results.items():
+        forms_out[form] = {"path": r["path"], "dtype": r["dtype"], "views_per_pass": r["views_per_pass"],
+                           "z_unroll": r["z_unroll"], "ms_per_step": round(float(r["step_ms"].mean()), 3),
+                           "gups_p50": round(r["gups_p50"], 2), "gups_p99": round(r["gups_p99"], 2),
+                           "gups_mean": round(r["gups_mean"], 2),
+                           "hbm_frac_algorithmic": round(
+                               r["gups_mean"] * 1e9 * (8.0 / r["views_per_pass"] +
+                                                       sc.W * sc.H * (4 if r["dtype"] == "f32" else 2) / v.L ** 3)
+                               / (HBM_PEAK_GBS * 1e9), 4),
+                           "error_vs_fp64_oracle": errors.get(form)}
+
+    line = {
+        "metric": "GUPS (voxel updates/s) at L=512, 496 views: fused/BF16 vs plain FP32; p50/p99",
+        "value": round(head["gups_mean"], 2),
+        "unit": "GUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(float(head["step_ms"].mean()), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random-ellipsoid phantom standing in for the RabbitCT dataset)",
+        "config": {"workload": wl.name, "L": v.L, "voxel_mm": v.voxel_size, "views": sc.n_views,
+                   "detector": [sc.W, sc.H], "form": "fused_f32", "parallelism": "single GPU"},
+        "p50_gups": round(head["gups_p50"], 2),
+        "p99_gups": round(head["gups_p99"], 2),
+        "forms": forms_out,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

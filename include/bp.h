@@ -1,0 +1,174 @@
+/*
+ * bp.h -- C ABI of the MI355X (gfx950) voxel-driven cone-beam back projector.
+ *
+ * The operation is the back projection of filtered, weighted projection
+ * images into a voxel volume that RabbitCT benchmarks (Hofmann, Treibig,
+ * Hager, Wellein, "Comparing the Performance of Different x86 SIMD
+ * Instruction Sets for a Medical Imaging Application on Modern Multi- and
+ * Manycore Chips", WPMVP'14, Sec. 4 and Sec. 4.1, Listing 1):
+ *
+ *   for every voxel (x, y, z) and every view k:
+ *     X       = origin + voxel_size * (x, y, z)         voxel centre (world, mm)
+ *     (u,v,w) = P_k (X, 1)                              3x4 projection matrix
+ *     if w > 0:
+ *       volume[x,y,z] += B_k(u/w, v/w) / w^2
+ *
+ * where B_k is the bilinear interpolant of image k with every pixel off the
+ * detector taken as 0 (the zero-padded buffer of Sec. 5.1.1) and integer
+ * pixel indices are floor(u/w), floor(v/w).  Arithmetic is FP32 (the
+ * reciprocal of w uses the hardware reciprocal, as Sec. 5.1 does on the
+ * CPUs); projections may be stored as FP32, FP16 or BF16 and are always
+ * interpolated and accumulated in FP32.
+ *
+ * Memory layouts (all arrays dense, no padding):
+ *   volume       FP32, voxel (x, y, z) at (z * ny + y) * nx + x  (x fastest,
+ *                the VOL[z*L*L + y*L + x] layout of Listing 1 when nx=ny=nz=L).
+ *   projections  n_views images of det_height rows by det_width columns of
+ *                the context's dtype; pixel (i, j) of view k at
+ *                (k * det_height + j) * det_width + i  (i = column, fast axis).
+ *   matrices     n_views row-major 3x4 FP32 matrices; P_k[r][c] at 12 k + 4 r + c.
+ *                (Listing 1 indexes its A column-major: A[3c + r] == P[r][c].)
+ *
+ * Ownership and concurrency: the caller owns every array.  volume,
+ * projections and matrices are DEVICE pointers on the context's device; they
+ * must stay valid and unmodified until the work enqueued on `stream` has
+ * completed.  A context owns device scratch (per-view constants and the
+ * zero-padded staging copy of the projections) that every call reuses, so
+ * calls on one context must not overlap: use one context per stream that
+ * runs concurrently.  Contexts are cheap.
+ *
+ * Errors: argument checks run on the host before anything is enqueued; a
+ * call that returns anything but BP_OK has enqueued nothing.  Device faults
+ * surface at the caller's next synchronisation of `stream`.
+ * bp_last_error(ctx) describes the last failure of a call on that context.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bp_ctx_s *bp_ctx;
+
+typedef enum {
+    BP_OK = 0,
+    BP_ERR_INVALID_ARG = 1,   /* null pointer, bad size, non-finite geometry, ... */
+    BP_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve */
+    BP_ERR_OUT_OF_MEMORY = 3, /* device scratch could not be allocated */
+    BP_ERR_DEVICE = 4,        /* HIP runtime error outside a launch */
+    BP_ERR_LAUNCH = 5         /* a kernel launch was rejected */
+} bp_status;
+
+typedef enum { BP_F32 = 0, BP_F16 = 1, BP_BF16 = 2 } bp_dtype;
+
+/* How the views of a call reach the volume. */
+typedef enum {
+    BP_PATH_AUTO = 0,   /* the tuned choice for (dtype, volume size) */
+    BP_PATH_PLAIN = 1,  /* one volume pass per view, taps read from the caller's images
+                           with the per-tap detector bounds of Listing 1 (Sec. 4.1) */
+    BP_PATH_FUSED = 2   /* views_per_pass views per volume pass, accumulated in
+                           registers; taps read from a zero-padded staging copy
+                           (Sec. 5.1.1), so no per-tap bounds tests */
+} bp_path;
+
+typedef struct {
+    int device;           /* HIP device ordinal */
+    int det_width;        /* W, detector columns (1248 for the RabbitCT data) */
+    int det_height;       /* H, detector rows (960) */
+    bp_dtype proj_dtype;  /* storage type of the projections */
+    bp_path path;         /* BP_PATH_AUTO picks a path per call */
+    int views_per_pass;   /* K for BP_PATH_FUSED; 0 = tuned */
+    int z_unroll;         /* voxels per thread along z (1, 2, 4 or 8); 0 = tuned */
+} bp_config;
+
+/* Fill *cfg with defaults: device 0, 1248 x 960, FP32, AUTO, tuned K and z_unroll. */
+void bp_config_default(bp_config *cfg);
+
+/* Create a context on cfg->device.  Validates cfg; allocates nothing on the device yet. */
+bp_status bp_create(const bp_config *cfg, bp_ctx *out);
+
+/* Destroy a context and free its scratch.  Synchronises the context's device
+   first (its scratch may be in use by enqueued work).  NULL is a no-op. */
+bp_status bp_destroy(bp_ctx ctx);
+
+/*
+ * Accumulate the back projection of n_views images into an L x L x L volume
+ * (the spec entry point; equivalent to bp_backproject_box with
+ * nx = ny = nz = L).
+ *
+ *   volume      device FP32, L^3, ACCUMULATED (+=): zero it first for a fresh
+ *               reconstruction; calls over consecutive chunks of views add up
+ *               (view streaming and resume).  Must be 4-byte aligned.
+ *   projections device, n_views images of the context's dtype and size.
+ *   matrices    device FP32, n_views * 12.
+ *   n_views     >= 1.
+ *   L           >= 1, L^3 < 2^31.
+ *   voxel_size  MM of Listing 1, > 0 and finite.
+ *   origin      HOST pointer to 3 floats: world position of the centre of
+ *               voxel (0, 0, 0).  The centred volume of Listing 1 has
+ *               origin = -(L - 1) / 2 * voxel_size on each axis.
+ *   stream      hipStream_t to enqueue on; NULL = the null stream.
+ */
+bp_status bp_backproject(bp_ctx ctx, float *volume, const void *projections,
+                         const float *matrices, int n_views, int L, float voxel_size,
+                         const float origin[3], void *stream);
+
+/* As bp_backproject for an nx x ny x nz box of voxels (e.g. a z-slab of a
+   larger volume, whose origin is the world centre of the box's first voxel). */
+bp_status bp_backproject_box(bp_ctx ctx, float *volume, int nx, int ny, int nz,
+                             const void *projections, const float *matrices, int n_views,
+                             float voxel_size, const float origin[3], void *stream);
+
+/* Override the per-call choices of a context (path, K, z_unroll); 0 keeps the tuned value. */
+bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll);
+
+/* The choices the next call of size nx*ny*nz with n_views views will use. */
+bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
+                        bp_path *path, int *views_per_pass, int *z_unroll);
+
+/*
+ * Compose the projection matrices of a circular cone-beam orbit on the host
+ * in FP64 and round them once to FP32 (the per-view A_i of Sec. 4, which
+ * RabbitCT ships with its data).  Convention: source at
+ * SID (cos t, sin t, 0), detector centre at -(SDD - SID)(cos t, sin t, 0),
+ * detector columns along (-sin t, cos t, 0), rows along (0, 0, 1), pixel
+ * (i, j) centred at ((W-1)/2, (H-1)/2) + (i, j) * pitch on the detector.
+ * Normalised so that w = depth along the principal ray / SID (w = 1 at the
+ * isocentre; 1/w^2 is then the FDK distance weight).
+ *
+ *   angles   host, n_views angles t_k in radians.
+ *   out_f64  host, n_views * 12 doubles, or NULL.
+ *   out_f32  host, n_views * 12 floats (rounded to nearest), or NULL.
+ * Returns BP_ERR_INVALID_ARG for non-positive or non-finite distances, pitch
+ * or detector size, or SDD <= 0.
+ */
+bp_status bp_circular_matrices(const double *angles, int n_views, double sid, double sdd,
+                               double pitch, int det_width, int det_height,
+                               double *out_f64, float *out_f32);
+
+/*
+ * Kernel timing for measurement.  When enabled, every kernel launch of the
+ * context is bracketed by two HIP events on the call's stream (the events add
+ * a few microseconds per launch).  bp_kernel_timing synchronises on those
+ * events and returns, for one kernel kind, the summed elapsed time in
+ * milliseconds and the number of launches since timing was last enabled or
+ * reset.  Kinds: 0 = back-projection pass, 1 = zero-padded staging copy,
+ * 2 = per-view constants.
+ */
+bp_status bp_enable_timing(bp_ctx ctx, int enable);
+bp_status bp_kernel_timing(bp_ctx ctx, int kind, double *total_ms, long long *launches);
+
+const char *bp_status_string(bp_status s);
+const char *bp_last_error(bp_ctx ctx);
+
+/* Library version, "major.minor.patch". */
+const char *bp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BP_H */

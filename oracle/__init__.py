@@ -19,11 +19,12 @@ Every function cites the passage of Hofmann, Treibig, Hager and Wellein,
 Medical Imaging Application on Modern Multi- and Manycore Chips" (WPMVP'14)
 that it follows.
 """
-from .bp import backproject, interpolate, tent_interpolate, load_library, build_library
+from .bp import backproject, backproject_points, interpolate, tent_interpolate, load_library, build_library
 from . import geometry, closed
 
 __all__ = [
     "backproject",
+    "backproject_points",
     "interpolate",
     "tent_interpolate",
     "load_library",

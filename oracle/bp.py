@@ -39,6 +39,12 @@ def _bind(lib):
         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
         ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
     ]
+    lib.oracle_backproject_points.restype = ctypes.c_int
+    lib.oracle_backproject_points.argtypes = [
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long,
+        ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+        ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+    ]
     lib.oracle_interpolate.restype = ctypes.c_double
     lib.oracle_interpolate.argtypes = [
         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -109,6 +115,23 @@ def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=No
     if rc != 0:
         raise ValueError("oracle_backproject rejected its arguments")
     return vol
+
+
+def backproject_points(proj, P, voxel_size, origin, xyz, threads=None, lib=None):
+    """FP64 back projection of a list of voxels ``xyz`` (M, 3) integer (x, y, z); returns (M,) FP64."""
+    lib = lib or load_library()
+    proj = np.ascontiguousarray(proj, dtype=np.float32)
+    n, H, W = proj.shape
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(n, 12))
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros(xyz.shape[0], dtype=np.float64)
+    o = np.ascontiguousarray(np.asarray(origin, dtype=np.float64).reshape(3))
+    rc = lib.oracle_backproject_points(out.ctypes.data, xyz.ctypes.data, xyz.shape[0], proj.ctypes.data, W, H, n,
+                                       P.ctypes.data, float(voxel_size), o.ctypes.data,
+                                       int(threads if threads is not None else default_threads()))
+    if rc != 0:
+        raise ValueError("oracle_backproject_points rejected its arguments")
+    return out
 
 
 def interpolate(img, ix, iy, lib=None):

@@ -181,6 +181,81 @@ int oracle_backproject(double *vol, int x0, int y0, int z0, int nx, int ny, int 
     return 0;
 }
 
+typedef struct {
+    double *out;
+    const int *xyz;
+    long n;
+    const float *proj;
+    int W, H, n_views;
+    const double *P;
+    double MM;
+    double O[3];
+    long first, step;
+} points_job_t;
+
+static void *run_points(void *arg)
+{
+    const points_job_t *jb = (const points_job_t *)arg;
+    const long img_size = (long)jb->W * jb->H;
+    for (long m = jb->first; m < jb->n; m += jb->step) {
+        double wx = jb->O[0] + jb->MM * (double)jb->xyz[3 * m];
+        double wy = jb->O[1] + jb->MM * (double)jb->xyz[3 * m + 1];
+        double wz = jb->O[2] + jb->MM * (double)jb->xyz[3 * m + 2];
+        double sum = jb->out[m];
+        for (int k = 0; k < jb->n_views; ++k)
+            sum += contribution(jb->proj + k * img_size, jb->W, jb->H, jb->P + 12 * (long)k, wx, wy, wz);
+        jb->out[m] = sum;
+    }
+    return NULL;
+}
+
+/*
+ * The same back projection for an arbitrary list of voxels: out[m] += sum over
+ * views for voxel (xyz[3m], xyz[3m+1], xyz[3m+2]).  Used to sample a large
+ * volume uniformly.  Returns 0, or -1 for an invalid argument.
+ */
+int oracle_backproject_points(double *out, const int *xyz, long n, const float *proj, int W, int H,
+                              int n_views, const double *P, double MM, const double *O, int n_threads)
+{
+    if (!out || !xyz || !proj || !P || !O || n < 0 || W < 1 || H < 1 || n_views < 0)
+        return -1;
+    if (n_threads <= 0)
+        n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > n)
+        n_threads = n > 0 ? (int)n : 1;
+    points_job_t *jobs = (points_job_t *)calloc((size_t)n_threads, sizeof(points_job_t));
+    pthread_t *tid = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !tid) {
+        free(jobs);
+        free(tid);
+        return -1;
+    }
+    for (int t = 0; t < n_threads; ++t) {
+        points_job_t *jb = &jobs[t];
+        jb->out = out; jb->xyz = xyz; jb->n = n;
+        jb->proj = proj; jb->W = W; jb->H = H; jb->n_views = n_views;
+        jb->P = P; jb->MM = MM;
+        jb->O[0] = O[0]; jb->O[1] = O[1]; jb->O[2] = O[2];
+        jb->first = t; jb->step = n_threads;
+    }
+    int started = 0;
+    for (int t = 1; t < n_threads; ++t) {
+        if (pthread_create(&tid[t], NULL, run_points, &jobs[t]) != 0)
+            break;
+        started = t;
+    }
+    for (int t = started + 1; t < n_threads; ++t)
+        run_points(&jobs[t]);
+    run_points(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tid[t], NULL);
+    free(jobs);
+    free(tid);
+    return 0;
+}
+
 /* Bilinear interpolant of one zero-extended image at one position (exported for pins). */
 double oracle_interpolate(const float *img, int W, int H, double ix, double iy)
 {

@@ -1,0 +1,380 @@
+// bp_api.cpp -- the C ABI declared in include/bp.h: argument validation,
+// per-context scratch, the choice of path / views per pass / z-unroll, and
+// the launch sequence of one call.
+#include "../../include/bp.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bp_internal.h"
+
+struct bp_ctx_s {
+    bp_config cfg;
+    std::string last_error;
+    // scratch, grown on demand, freed by bp_destroy
+    bp::ViewConst* d_views = nullptr;
+    size_t views_cap = 0;  // records
+    void* d_pad = nullptr;
+    size_t pad_cap = 0;  // bytes
+    // overrides set by bp_set_tuning (0 = tuned)
+    bp_path path_override = BP_PATH_AUTO;
+    int k_override = 0;
+    int zu_override = 0;
+    // kernel timing (bp_enable_timing): event pairs per kernel kind
+    bool timing = false;
+    struct Pair {
+        hipEvent_t start, stop;
+    };
+    std::vector<Pair> pending[3];
+    double total_ms[3] = {0, 0, 0};
+    long long launches[3] = {0, 0, 0};
+    std::vector<hipEvent_t> event_pool;
+    // staging layout of the fused path (BP_FUSED_LAYOUT=pairs|patch, read at bp_create)
+    bp::Layout fused_layout = bp::Layout::Patch;
+};
+
+namespace {
+
+const char* const kVersion = "0.1.0";
+
+bp_status fail(bp_ctx ctx, bp_status st, const std::string& msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+// Switch to the context's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+bool valid_zu(int zu) { return zu == 1 || zu == 2 || zu == 4 || zu == 8; }
+
+bool fault_injected(const char* what)
+{
+    const char* v = std::getenv("BP_FAULT_INJECT");
+    return v && std::strcmp(v, what) == 0;
+}
+
+bp_status ensure(bp_ctx ctx, void** ptr, size_t* cap, size_t need, const char* what)
+{
+    if (need <= *cap) return BP_OK;
+    if (*ptr) {
+        // Work already enqueued may still read the old buffer.
+        if (hipDeviceSynchronize() != hipSuccess || hipFree(*ptr) != hipSuccess)
+            return fail(ctx, BP_ERR_DEVICE, std::string("freeing scratch for ") + what + " failed");
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    if (fault_injected("alloc") || hipMalloc(ptr, need) != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, BP_ERR_OUT_OF_MEMORY,
+                    std::string("cannot allocate ") + std::to_string(need) + " bytes of scratch for " + what);
+    }
+    *cap = need;
+    return BP_OK;
+}
+
+hipEvent_t take_event(bp_ctx ctx)
+{
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket one launch with events when timing is on.
+template <class F>
+hipError_t timed(bp_ctx ctx, int kind, hipStream_t s, F&& launch)
+{
+    if (!ctx->timing) return launch();
+    bp_ctx_s::Pair p{take_event(ctx), take_event(ctx)};
+    if (!p.start || !p.stop) return hipErrorOutOfMemory;
+    (void)hipEventRecord(p.start, s);
+    const hipError_t e = launch();
+    (void)hipEventRecord(p.stop, s);
+    ctx->pending[kind].push_back(p);
+    return e;
+}
+
+// Fold finished event pairs into the totals (synchronises on each stop event).
+bp_status drain_timing(bp_ctx ctx)
+{
+    bp_status st = BP_OK;
+    for (int k = 0; k < 3; ++k) {
+        for (auto& p : ctx->pending[k]) {
+            float ms = 0.0f;
+            if (hipEventSynchronize(p.stop) != hipSuccess || hipEventElapsedTime(&ms, p.start, p.stop) != hipSuccess)
+                st = BP_ERR_DEVICE;
+            ctx->total_ms[k] += ms;
+            ctx->launches[k] += 1;
+            ctx->event_pool.push_back(p.start);
+            ctx->event_pool.push_back(p.stop);
+        }
+        ctx->pending[k].clear();
+    }
+    return st;
+}
+
+struct Plan {
+    bp_path path;
+    int k;
+    int zu;
+};
+
+// Tuned defaults.  Measured on MI355X; BP_PATH_AUTO resolves here unless
+// bp_set_tuning or the context's config fixes a choice.
+Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
+{
+    Plan p;
+    p.path = ctx->path_override != BP_PATH_AUTO ? ctx->path_override : ctx->cfg.path;
+    if (p.path == BP_PATH_AUTO) p.path = BP_PATH_FUSED;
+    p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
+    if (p.k <= 0) p.k = 32;
+    if (p.path == BP_PATH_PLAIN) p.k = 1;
+    if (p.k > n_views) p.k = n_views;
+    p.zu = ctx->zu_override > 0 ? ctx->zu_override : ctx->cfg.z_unroll;
+    if (p.zu <= 0) p.zu = 8;
+    while (p.zu > 1 && p.zu > nz) p.zu >>= 1;
+    (void)nx;
+    (void)ny;
+    return p;
+}
+
+bp::Dtype to_dt(bp_dtype d) { return static_cast<bp::Dtype>(static_cast<int>(d)); }
+
+size_t elem_bytes(bp_dtype d) { return d == BP_F32 ? 4 : 2; }
+
+}  // namespace
+
+extern "C" {
+
+void bp_config_default(bp_config* cfg)
+{
+    if (!cfg) return;
+    cfg->device = 0;
+    cfg->det_width = 1248;
+    cfg->det_height = 960;
+    cfg->proj_dtype = BP_F32;
+    cfg->path = BP_PATH_AUTO;
+    cfg->views_per_pass = 0;
+    cfg->z_unroll = 0;
+}
+
+const char* bp_version(void) { return kVersion; }
+
+const char* bp_status_string(bp_status s)
+{
+    switch (s) {
+    case BP_OK: return "ok";
+    case BP_ERR_INVALID_ARG: return "invalid argument";
+    case BP_ERR_UNSUPPORTED: return "unsupported";
+    case BP_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case BP_ERR_DEVICE: return "device error";
+    case BP_ERR_LAUNCH: return "kernel launch failed";
+    }
+    return "unknown status";
+}
+
+const char* bp_last_error(bp_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+bp_status bp_create(const bp_config* cfg, bp_ctx* out)
+{
+    if (!out) return BP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg) return BP_ERR_INVALID_ARG;
+    if (cfg->det_width < 1 || cfg->det_height < 1 || cfg->det_width > (1 << 20) ||
+        cfg->det_height > (1 << 20))
+        return BP_ERR_INVALID_ARG;
+    if ((size_t)(cfg->det_width + 3) * (size_t)(cfg->det_height + 3) * 4u >= (size_t)1 << 31)
+        return BP_ERR_UNSUPPORTED;  // one view must fit a 32-bit buffer offset
+    if (cfg->proj_dtype != BP_F32 && cfg->proj_dtype != BP_F16 && cfg->proj_dtype != BP_BF16)
+        return BP_ERR_INVALID_ARG;
+    if (cfg->path != BP_PATH_AUTO && cfg->path != BP_PATH_PLAIN && cfg->path != BP_PATH_FUSED)
+        return BP_ERR_INVALID_ARG;
+    if (cfg->views_per_pass < 0 || (cfg->z_unroll != 0 && !valid_zu(cfg->z_unroll)))
+        return BP_ERR_INVALID_ARG;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev < 1) {
+        (void)hipGetLastError();
+        return BP_ERR_DEVICE;
+    }
+    if (cfg->device < 0 || cfg->device >= n_dev) return BP_ERR_INVALID_ARG;
+    bp_ctx ctx = new (std::nothrow) bp_ctx_s();
+    if (!ctx) return BP_ERR_OUT_OF_MEMORY;
+    ctx->cfg = *cfg;
+    if (const char* l = std::getenv("BP_FUSED_LAYOUT")) {
+        if (std::strcmp(l, "pairs") == 0) ctx->fused_layout = bp::Layout::Pairs;
+    }
+    *out = ctx;
+    return BP_OK;
+}
+
+bp_status bp_destroy(bp_ctx ctx)
+{
+    if (!ctx) return BP_OK;
+    bp_status st = BP_OK;
+    {
+        DeviceGuard g(ctx->cfg.device);
+        if (drain_timing(ctx) != BP_OK) st = BP_ERR_DEVICE;
+        for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+        ctx->event_pool.clear();
+        if (ctx->d_views || ctx->d_pad) {
+            if (hipDeviceSynchronize() != hipSuccess) st = BP_ERR_DEVICE;
+            if (ctx->d_views && hipFree(ctx->d_views) != hipSuccess) st = BP_ERR_DEVICE;
+            if (ctx->d_pad && hipFree(ctx->d_pad) != hipSuccess) st = BP_ERR_DEVICE;
+        }
+    }
+    delete ctx;
+    return st;
+}
+
+bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (path != BP_PATH_AUTO && path != BP_PATH_PLAIN && path != BP_PATH_FUSED)
+        return fail(ctx, BP_ERR_INVALID_ARG, "unknown path");
+    if (views_per_pass < 0) return fail(ctx, BP_ERR_INVALID_ARG, "views_per_pass < 0");
+    if (z_unroll != 0 && !valid_zu(z_unroll)) return fail(ctx, BP_ERR_INVALID_ARG, "z_unroll not in {1,2,4,8}");
+    ctx->path_override = path;
+    ctx->k_override = views_per_pass;
+    ctx->zu_override = z_unroll;
+    return BP_OK;
+}
+
+bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path* path, int* views_per_pass,
+                        int* z_unroll)
+{
+    if (!ctx || nx < 1 || ny < 1 || nz < 1 || n_views < 1) return BP_ERR_INVALID_ARG;
+    const Plan p = plan_for(ctx, nx, ny, nz, n_views);
+    if (path) *path = p.path;
+    if (views_per_pass) *views_per_pass = p.k;
+    if (z_unroll) *z_unroll = p.zu;
+    return BP_OK;
+}
+
+bp_status bp_enable_timing(bp_ctx ctx, int enable)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->cfg.device);
+    const bp_status st = drain_timing(ctx);
+    for (int k = 0; k < 3; ++k) {
+        ctx->total_ms[k] = 0.0;
+        ctx->launches[k] = 0;
+    }
+    ctx->timing = enable != 0;
+    return st;
+}
+
+bp_status bp_kernel_timing(bp_ctx ctx, int kind, double* total_ms, long long* launches)
+{
+    if (!ctx || kind < 0 || kind > 2) return BP_ERR_INVALID_ARG;
+    DeviceGuard g(ctx->cfg.device);
+    const bp_status st = drain_timing(ctx);
+    if (total_ms) *total_ms = ctx->total_ms[kind];
+    if (launches) *launches = ctx->launches[kind];
+    return st != BP_OK ? fail(ctx, st, "timing events failed") : BP_OK;
+}
+
+bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, const void* projections,
+                             const float* matrices, int n_views, float voxel_size, const float origin[3],
+                             void* stream)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (!volume || !projections || !matrices || !origin)
+        return fail(ctx, BP_ERR_INVALID_ARG, "null pointer argument");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, BP_ERR_INVALID_ARG, "volume dimensions must be >= 1");
+    if ((uint64_t)nx * (uint64_t)ny * (uint64_t)nz >= ((uint64_t)1 << 40))
+        return fail(ctx, BP_ERR_INVALID_ARG, "volume too large");
+    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24))
+        return fail(ctx, BP_ERR_INVALID_ARG, "volume edge beyond 2^24 voxels");
+    if (n_views < 1) return fail(ctx, BP_ERR_INVALID_ARG, "n_views must be >= 1");
+    if (!std::isfinite(voxel_size) || !(voxel_size > 0.0f))
+        return fail(ctx, BP_ERR_INVALID_ARG, "voxel_size must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(origin[a])) return fail(ctx, BP_ERR_INVALID_ARG, "origin must be finite");
+    if (reinterpret_cast<uintptr_t>(volume) % 4 != 0 || reinterpret_cast<uintptr_t>(matrices) % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(projections) % elem_bytes(ctx->cfg.proj_dtype) != 0)
+        return fail(ctx, BP_ERR_INVALID_ARG, "misaligned device pointer");
+
+    const int W = ctx->cfg.det_width, H = ctx->cfg.det_height;
+    const Plan plan = plan_for(ctx, nx, ny, nz, n_views);
+    const bp::Box box{nx, ny, nz, voxel_size, origin[0], origin[1], origin[2]};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bp::Dtype dt = to_dt(ctx->cfg.proj_dtype);
+
+    DeviceGuard g(ctx->cfg.device);
+    if (!g.ok) return fail(ctx, BP_ERR_DEVICE, "cannot select the context's device");
+
+    bp_status st = ensure(ctx, reinterpret_cast<void**>(&ctx->d_views), &ctx->views_cap,
+                          sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
+    if (st != BP_OK) return st;
+    if (ctx->views_cap < sizeof(bp::ViewConst) * (size_t)n_views) return BP_ERR_OUT_OF_MEMORY;
+    const bp::Layout layout = plan.path == BP_PATH_FUSED ? ctx->fused_layout : bp::Layout::Checked;
+    if (layout != bp::Layout::Checked) {
+        st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, bp::staged_view_bytes(layout, W, H) * (size_t)plan.k,
+                    "staged projections");
+        if (st != BP_OK) return st;
+    }
+
+    if (timed(ctx, 2, s, [&] { return bp::launch_prep_views(matrices, n_views, box, ctx->d_views, s); }) !=
+        hipSuccess)
+        return fail(ctx, BP_ERR_LAUNCH, "view-constant kernel launch failed");
+
+    const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
+    for (int k0 = 0; k0 < n_views; k0 += plan.k) {
+        const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
+        const void* src_views = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;
+        hipError_t e;
+        if (layout != bp::Layout::Checked) {
+            e = timed(ctx, 1, s, [&] {
+                return layout == bp::Layout::Patch ? bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s)
+                                                   : bp::launch_pad(dt, src_views, W, H, kc, ctx->d_pad, s);
+            });
+            if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
+            e = timed(ctx, 0, s, [&] {
+                return bp::launch_backproject(dt, layout, plan.zu, volume, box, ctx->d_views + k0, kc, ctx->d_pad, W, H, s);
+            });
+        } else {
+            e = timed(ctx, 0, s, [&] {
+                return bp::launch_backproject(dt, layout, plan.zu, volume, box, ctx->d_views + k0, kc, src_views, W, H, s);
+            });
+        }
+        if (e != hipSuccess)
+            return fail(ctx, BP_ERR_LAUNCH, std::string("back-projection kernel: ") + hipGetErrorString(e));
+    }
+    return BP_OK;
+}
+
+bp_status bp_backproject(bp_ctx ctx, float* volume, const void* projections, const float* matrices, int n_views,
+                         int L, float voxel_size, const float origin[3], void* stream)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (L < 1) return fail(ctx, BP_ERR_INVALID_ARG, "L must be >= 1");
+    if ((uint64_t)L * L * L >= ((uint64_t)1 << 31)) return fail(ctx, BP_ERR_INVALID_ARG, "L^3 must be < 2^31");
+    return bp_backproject_box(ctx, volume, L, L, L, projections, matrices, n_views, voxel_size, origin, stream);
+}
+
+}  // extern "C"

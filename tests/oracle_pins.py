@@ -241,3 +241,20 @@ def pin_invariants(lib):
 
 ALL_PINS = [pin_handworked, pin_tent, pin_bruteforce, pin_constant, pin_affine, pin_impulse,
             pin_orthographic, pin_invariants]
+
+
+def pin_points_equal_blocks(lib):
+    """The voxel-list entry computes exactly what the block entry computes for the same voxels."""
+    _, P = small_scan(n_views=4)
+    P = _P32(P)
+    L, vs = 11, 20.0
+    origin = [-(L - 1) / 2 * vs] * 3
+    rng = np.random.default_rng(12)
+    proj = rng.uniform(-1, 1, size=(4, SMALL_SCAN["H"], SMALL_SCAN["W"])).astype(np.float32)
+    V = oracle.backproject(proj, P, L, vs, origin, lib=lib)
+    xyz = rng.integers(0, L, size=(50, 3))
+    got = oracle.backproject_points(proj, P, vs, origin, xyz, lib=lib)
+    assert np.array_equal(got, V[xyz[:, 2], xyz[:, 1], xyz[:, 0]])
+
+
+ALL_PINS.append(pin_points_equal_blocks)

@@ -32,7 +32,10 @@ MUTANTS = {
                          "double v = A[4] * wx + A[5] * wy + A[6] * wz;"),
     "edge_guard_open": ("if (!(ix > -1.0 && ix < (double)W && iy > -1.0 && iy < (double)H))",
                         "if (!(ix > 0.0 && ix < (double)W && iy > -1.0 && iy < (double)H))"),
-    "skip_first_view": ("for (int k = 0; k < jb->n_views; ++k)", "for (int k = 1; k < jb->n_views; ++k)"),
+    "skip_first_view": ("                for (int k = 0; k < jb->n_views; ++k)",
+                        "                for (int k = 1; k < jb->n_views; ++k)"),
+    "points_skip_last_view": ("        for (int k = 0; k < jb->n_views; ++k)\n            sum +=",
+                              "        for (int k = 0; k < jb->n_views - 1; ++k)\n            sum +="),
     "overwrite_not_accumulate": ("double sum = *voxel;", "double sum = 0.0;"),
 }
 

@@ -44,8 +44,14 @@ def parse():
     ap.add_argument("--workload", default="fdk_l512_v496_f32")
     ap.add_argument("--k", type=int, default=0, help="views per pass for fused forms (0 = tuned)")
     ap.add_argument("--zu", type=int, default=0, help="z-unroll (0 = tuned)")
+    ap.add_argument("--tx", type=int, default=0, help="block tile width along x (0 = tuned)")
+    ap.add_argument("--no-xcd-order", action="store_true", help="time with plain block order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-block", type=int, default=128, help="edge of the centre block the oracle times")
+    ap.add_argument("--no-cull", action="store_true", help="time without the clipping mask")
+    ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
+    ap.add_argument("--cpu-block", type=int, default=160, help="edge of the centre block the oracle times")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -53,7 +59,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu):
+def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
+              no_column=False, no_xcd_order=False):
     path, dt = form.split("_")
     proj = proj_by_dtype[dt]
     n, H, W = proj.shape
@@ -62,7 +69,8 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu):
     vol = torch.zeros((L, L, L), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
     ctx = bp.Context(W, H, dt)
-    ctx.set_tuning(path, k, zu)
+    ctx.set_tuning(path, k, zu, tx)
+    ctx.set_options(no_cull=no_cull, no_column=no_column, no_xcd_order=no_xcd_order)
     plan = ctx.plan(L, L, L, n)
     for _ in range(warmup):
         ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
@@ -86,6 +94,7 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu):
     out = vol / float(steps)  # every step added the same reconstruction
     return {
         "path": plan.path, "dtype": dt, "views_per_pass": plan.views_per_pass, "z_unroll": plan.z_unroll,
+        "tile_x": plan.tile_x,
         "step_ms": step_ms, "wall_s": wall, "kernels": kern, "volume": out,
     }
 
@@ -110,6 +119,14 @@ def main():
     proj32 = synth.filtered_projections(sc, synth.random_ellipsoids(wl.phantom_seed), device=dev)
     torch.cuda.synchronize()
     log(f"bench: inputs generated on the GPU in {time.perf_counter() - t:.1f} s")
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration: 3 x {args.copy_calibration} MiB device-to-device")
+        del src, dst
     forms = [f for f in args.forms.split(",") if f]
     proj_by_dtype = {"f32": proj32}
     if any(f.endswith("bf16") for f in forms):
@@ -122,13 +139,14 @@ def main():
     updates = float(v.L) ** 3 * sc.n_views
     results = {}
     for form in forms:
-        r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu)
+        r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
+                      args.no_cull, args.no_column, args.no_xcd_order)
         ms = r["step_ms"]
         r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9
         r["gups_p99"] = updates / (np.percentile(ms, 99) * 1e-3) / 1e9
         log(f"bench: {form}: {ms.mean():.2f} ms/step  p50 {r['gups_p50']:.1f} GUPS  p99 {r['gups_p99']:.1f} GUPS  "
-            f"(path {r['path']} K={r['views_per_pass']} ZU={r['z_unroll']}) kernels {r['kernels']}")
+            f"(path {r['path']} K={r['views_per_pass']} ZU={r['z_unroll']} TX={r['tile_x']}) kernels {r['kernels']}")
         results[form] = r
 
     # CPU baseline: the oracle on the centre block, on this host's cores.
@@ -172,7 +190,8 @@ def main():
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {"path": r["path"], "dtype": r["dtype"], "views_per_pass": r["views_per_pass"],
-                           "z_unroll": r["z_unroll"], "ms_per_step": round(float(r["step_ms"].mean()), 3),
+                           "z_unroll": r["z_unroll"], "tile_x": r["tile_x"],
+                           "ms_per_step": round(float(r["step_ms"].mean()), 3),
                            "gups_p50": round(r["gups_p50"], 2), "gups_p99": round(r["gups_p99"], 2),
                            "gups_mean": round(r["gups_mean"], 2),
                            "hbm_frac_algorithmic": round(

@@ -82,9 +82,11 @@ typedef struct {
     bp_path path;         /* BP_PATH_AUTO picks a path per call */
     int views_per_pass;   /* K for BP_PATH_FUSED; 0 = tuned */
     int z_unroll;         /* voxels per thread along z (1, 2, 4 or 8); 0 = tuned */
+    int tile_x;           /* columns along x per 256-thread block (8, 16, 32 or 64; the block is
+                             tile_x x 256/tile_x columns); 0 = tuned.  BP_PATH_PLAIN uses 64. */
 } bp_config;
 
-/* Fill *cfg with defaults: device 0, 1248 x 960, FP32, AUTO, tuned K and z_unroll. */
+/* Fill *cfg with defaults: device 0, 1248 x 960, FP32, AUTO, tuned K, z_unroll and tile_x. */
 void bp_config_default(bp_config *cfg);
 
 /* Create a context on cfg->device.  Validates cfg; allocates nothing on the device yet. */
@@ -122,12 +124,27 @@ bp_status bp_backproject_box(bp_ctx ctx, float *volume, int nx, int ny, int nz,
                              const void *projections, const float *matrices, int n_views,
                              float voxel_size, const float origin[3], void *stream);
 
-/* Override the per-call choices of a context (path, K, z_unroll); 0 keeps the tuned value. */
-bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll);
+/* Override the per-call choices of a context (path, K, z_unroll, tile_x); 0 keeps the tuned value. */
+bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll, int tile_x);
+
+/*
+ * Options (bit flags, default 0 = all optimisations on; results are equal
+ * either way, up to FP32 rounding for BP_OPT_NO_COLUMN):
+ *   BP_OPT_NO_CULL    do not skip (tile, view) pairs whose whole tile projects
+ *                     off the detector (the clipping mask of Sec. 5)
+ *   BP_OPT_NO_COLUMN  do not specialise views whose matrix has P[0][2] = P[2][2] = 0
+ *                     (u and w constant along z, as for a circular orbit about z)
+ *   BP_OPT_NO_XCD_ORDER  number blocks in plain tile order instead of dealing
+ *                     contiguous z-ranges of tiles to the 8 XCDs
+ */
+#define BP_OPT_NO_CULL 1
+#define BP_OPT_NO_COLUMN 2
+#define BP_OPT_NO_XCD_ORDER 4
+bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
-                        bp_path *path, int *views_per_pass, int *z_unroll);
+                        bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x);
 
 /*
  * Compose the projection matrices of a circular cone-beam orbit on the host

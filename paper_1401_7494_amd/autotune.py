@@ -20,6 +20,7 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 
 K_CANDIDATES = (1, 2, 4, 8, 16, 32, 64)
 ZU_CANDIDATES = (1, 2, 4, 8)
+TX_CANDIDATES = (8, 16, 32, 64)
 
 
 @dataclass(frozen=True)
@@ -27,6 +28,7 @@ class Candidate:
     path: str
     views_per_pass: int
     z_unroll: int
+    tile_x: int = 64
 
 
 @dataclass(frozen=True)
@@ -47,14 +49,16 @@ class Problem:
 @dataclass
 class Result:
     best: Candidate
-    timings_ms: dict = field(default_factory=dict)  # "path/K/ZU" -> median ms
+    timings_ms: dict = field(default_factory=dict)  # "path/K/ZU/TX" -> median ms
 
 
-def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, include_plain=True):
+def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, txs=TX_CANDIDATES, include_plain=True):
+    """Plain passes (64-wide tiles) and fused passes over K x ZU x tile width."""
+    zus = [zu for zu in zus if zu <= max(problem.nz, 1)]
     out = []
     if include_plain:
-        out += [Candidate("plain", 1, zu) for zu in zus if zu <= max(problem.nz, 1)]
-    out += [Candidate("fused", k, zu) for k in ks if k <= problem.n_views for zu in zus if zu <= max(problem.nz, 1)]
+        out += [Candidate("plain", 1, zu, 64) for zu in zus]
+    out += [Candidate("fused", k, zu, tx) for k in ks if k <= problem.n_views for zu in zus for tx in txs]
     return out
 
 
@@ -68,10 +72,10 @@ def search(problem: Problem, time_fn, cands=None, reps: int = 3, warmup: int = 1
         for _ in range(warmup):
             time_fn(c)
         ms = statistics.median(time_fn(c) for _ in range(reps))
-        timings[f"{c.path}/{c.views_per_pass}/{c.z_unroll}"] = ms
+        timings[f"{c.path}/{c.views_per_pass}/{c.z_unroll}/{c.tile_x}"] = ms
     best_key = min(timings, key=timings.get)
-    path, k, zu = best_key.split("/")
-    return Result(Candidate(path, int(k), int(zu)), timings)
+    path, k, zu, tx = best_key.split("/")
+    return Result(Candidate(path, int(k), int(zu), int(tx)), timings)
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:
@@ -99,7 +103,7 @@ def device_timer(ctx, volume, projections, matrices, voxel_size, origin, torch):
     """A ``time_fn`` that runs one call on the device and returns its time in ms (HIP events)."""
 
     def run(c: Candidate) -> float:
-        ctx.set_tuning(c.path, c.views_per_pass, c.z_unroll)
+        ctx.set_tuning(c.path, c.views_per_pass, c.z_unroll, c.tile_x)
         s = torch.cuda.current_stream()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -129,4 +133,54 @@ def tune_on_device(ctx, volume, projections, matrices, voxel_size, origin, cands
 
 
 def apply(ctx, cand: Candidate) -> None:
-    ctx.set_tuning(cand.path, cand.views_per_pass, cand.z_unroll)
+    ctx.set_tuning(cand.path, cand.views_per_pass, cand.z_unroll, cand.tile_x)
+
+
+def _csv_ints(s):
+    return tuple(int(v) for v in s.split(",") if v)
+
+
+def main(argv=None):
+    """Tune one standard workload on the GPU: ``python -m paper_1401_7494_amd.autotune --workload ...``."""
+    import argparse
+    import sys
+
+    import torch
+
+    from . import bp, synth
+
+    ap = argparse.ArgumentParser(description="autotune the fused back projection for one workload")
+    ap.add_argument("--workload", default="fdk_l512_v496_f32")
+    ap.add_argument("--dtype", default=None, help="storage dtype (default: the workload's)")
+    ap.add_argument("--ks", default="8,16,32,64")
+    ap.add_argument("--zus", default="4,8")
+    ap.add_argument("--txs", default="8,16,32,64")
+    ap.add_argument("--plain", action="store_true", help="also time the plain path")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    args = ap.parse_args(argv)
+    wl = synth.WORKLOADS[args.workload]
+    dtype = args.dtype or wl.dtype
+    dev = torch.device("cuda:0")
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    proj = synth.filtered_projections(wl.scanner, synth.random_ellipsoids(wl.phantom_seed), device=dev,
+                                      out_dtype=tdt)
+    _, P32 = bp.circular_matrices(*wl.scanner.geometry_args())
+    mats = torch.from_numpy(P32).to(dev)
+    v = wl.volume
+    vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=dev)
+    problem = Problem(v.L, v.L, v.L, wl.scanner.n_views, dtype, wl.scanner.W, wl.scanner.H)
+    cands = candidates(problem, _csv_ints(args.ks), _csv_ints(args.zus), _csv_ints(args.txs), args.plain)
+    with bp.Context(wl.scanner.W, wl.scanner.H, dtype) as ctx:
+        res = search(problem, device_timer(ctx, vol, proj, mats, v.voxel_size, v.origin, torch), cands, args.reps)
+    updates = v.L ** 3 * wl.scanner.n_views
+    for key, ms in sorted(res.timings_ms.items(), key=lambda kv: kv[1]):
+        print(f"autotune {wl.name} {dtype} {key}: {ms:.3f} ms  {updates / ms / 1e6:.1f} GUPS", flush=True)
+    print(f"autotune best: {res.best}", flush=True)
+    if args.cache:
+        store(problem.key(torch.cuda.get_device_name(dev)), res, args.cache)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -35,6 +35,7 @@ class BpConfig(ctypes.Structure):
         ("path", _c_int),
         ("views_per_pass", _c_int),
         ("z_unroll", _c_int),
+        ("tile_x", _c_int),
     ]
 
 
@@ -45,9 +46,10 @@ SIGNATURES = {
     "bp_backproject": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_float, ctypes.POINTER(_c_float), _vp]),
     "bp_backproject_box": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp, _c_int, _c_float,
                                     ctypes.POINTER(_c_float), _vp]),
-    "bp_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int]),
+    "bp_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
+    "bp_set_options": (_c_int, [_vp, _c_int]),
     "bp_query_plan": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
-                               ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+                               ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "bp_circular_matrices": (_c_int, [_vp, _c_int, _c_double, _c_double, _c_double, _c_int, _c_int, _vp, _vp]),
     "bp_enable_timing": (_c_int, [_vp, _c_int]),
     "bp_kernel_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong)]),
@@ -102,13 +104,14 @@ class Plan:
     path: str
     views_per_pass: int
     z_unroll: int
+    tile_x: int
 
 
 class Context:
     """One library context (one device, detector size and projection dtype)."""
 
     def __init__(self, det_width=1248, det_height=960, dtype="f32", device=0, path="auto",
-                 views_per_pass=0, z_unroll=0):
+                 views_per_pass=0, z_unroll=0, tile_x=0):
         L = lib()
         cfg = BpConfig()
         L.bp_config_default(ctypes.byref(cfg))
@@ -119,6 +122,7 @@ class Context:
         cfg.path = PATHS[path]
         cfg.views_per_pass = int(views_per_pass)
         cfg.z_unroll = int(z_unroll)
+        cfg.tile_x = int(tile_x)
         h = _vp()
         st = L.bp_create(ctypes.byref(cfg), ctypes.byref(h))
         if st != BP_OK:
@@ -154,8 +158,19 @@ class Context:
         if st != BP_OK:
             raise BPError(st, f"{what}: {status_string(st)}: {self.last_error()}")
 
-    def set_tuning(self, path="auto", views_per_pass=0, z_unroll=0):
-        self._check(lib().bp_set_tuning(self._h, PATHS[path], int(views_per_pass), int(z_unroll)), "bp_set_tuning")
+    def set_tuning(self, path="auto", views_per_pass=0, z_unroll=0, tile_x=0):
+        self._check(lib().bp_set_tuning(self._h, PATHS[path], int(views_per_pass), int(z_unroll), int(tile_x)),
+                    "bp_set_tuning")
+
+    OPT_NO_CULL = 1
+    OPT_NO_COLUMN = 2
+    OPT_NO_XCD_ORDER = 4
+
+    def set_options(self, no_cull: bool = False, no_column: bool = False, no_xcd_order: bool = False):
+        """Switch off the clipping mask, the column specialisation or the XCD tile order (all on by default)."""
+        flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
+                 | (self.OPT_NO_XCD_ORDER if no_xcd_order else 0))
+        self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     KERNELS = {"backproject": 0, "pad": 1, "views": 2}
 
@@ -171,10 +186,10 @@ class Context:
         return ms.value, n.value
 
     def plan(self, nx, ny, nz, n_views) -> Plan:
-        p, k, z = _c_int(), _c_int(), _c_int()
+        p, k, z, t = _c_int(), _c_int(), _c_int(), _c_int()
         self._check(lib().bp_query_plan(self._h, nx, ny, nz, n_views, ctypes.byref(p), ctypes.byref(k),
-                                        ctypes.byref(z)), "bp_query_plan")
-        return Plan(PATH_NAMES[p.value], k.value, z.value)
+                                        ctypes.byref(z), ctypes.byref(t)), "bp_query_plan")
+        return Plan(PATH_NAMES[p.value], k.value, z.value, t.value)
 
     def backproject(self, volume, projections, matrices, voxel_size, origin, stream=None) -> None:
         """Accumulate ``projections`` (N, H, W) into ``volume`` (nz, ny, nx), asynchronously on ``stream``.

@@ -23,10 +23,14 @@ struct bp_ctx_s {
     size_t views_cap = 0;  // records
     void* d_pad = nullptr;
     size_t pad_cap = 0;  // bytes
+    void* d_cull = nullptr;
+    size_t cull_cap = 0;  // bytes
+    int options = 0;      // BP_OPT_* flags
     // overrides set by bp_set_tuning (0 = tuned)
     bp_path path_override = BP_PATH_AUTO;
     int k_override = 0;
     int zu_override = 0;
+    int tx_override = 0;
     // kernel timing (bp_enable_timing): event pairs per kernel kind
     bool timing = false;
     struct Pair {
@@ -66,6 +70,7 @@ struct DeviceGuard {
 };
 
 bool valid_zu(int zu) { return zu == 1 || zu == 2 || zu == 4 || zu == 8; }
+bool valid_tx(int tx) { return tx == 8 || tx == 16 || tx == 32 || tx == 64; }
 
 bool fault_injected(const char* what)
 {
@@ -142,10 +147,11 @@ struct Plan {
     bp_path path;
     int k;
     int zu;
+    int tx;
 };
 
-// Tuned defaults.  Measured on MI355X; BP_PATH_AUTO resolves here unless
-// bp_set_tuning or the context's config fixes a choice.
+// Tuned defaults (measured on MI355X at L = 512, 496 views); BP_PATH_AUTO
+// resolves here unless bp_set_tuning or the context's config fixes a choice.
 Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
 {
     Plan p;
@@ -158,6 +164,10 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     p.zu = ctx->zu_override > 0 ? ctx->zu_override : ctx->cfg.z_unroll;
     if (p.zu <= 0) p.zu = 8;
     while (p.zu > 1 && p.zu > nz) p.zu >>= 1;
+    p.tx = ctx->tx_override > 0 ? ctx->tx_override : ctx->cfg.tile_x;
+    if (p.tx <= 0) p.tx = 16;
+    // the plain path and the pair layout come in 64-wide tiles only
+    if (p.path == BP_PATH_PLAIN || ctx->fused_layout != bp::Layout::Patch) p.tx = 64;
     (void)nx;
     (void)ny;
     return p;
@@ -181,6 +191,7 @@ void bp_config_default(bp_config* cfg)
     cfg->path = BP_PATH_AUTO;
     cfg->views_per_pass = 0;
     cfg->z_unroll = 0;
+    cfg->tile_x = 0;
 }
 
 const char* bp_version(void) { return kVersion; }
@@ -214,7 +225,8 @@ bp_status bp_create(const bp_config* cfg, bp_ctx* out)
         return BP_ERR_INVALID_ARG;
     if (cfg->path != BP_PATH_AUTO && cfg->path != BP_PATH_PLAIN && cfg->path != BP_PATH_FUSED)
         return BP_ERR_INVALID_ARG;
-    if (cfg->views_per_pass < 0 || (cfg->z_unroll != 0 && !valid_zu(cfg->z_unroll)))
+    if (cfg->views_per_pass < 0 || (cfg->z_unroll != 0 && !valid_zu(cfg->z_unroll)) ||
+        (cfg->tile_x != 0 && !valid_tx(cfg->tile_x)))
         return BP_ERR_INVALID_ARG;
     int n_dev = 0;
     if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev < 1) {
@@ -241,37 +253,50 @@ bp_status bp_destroy(bp_ctx ctx)
         if (drain_timing(ctx) != BP_OK) st = BP_ERR_DEVICE;
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
         ctx->event_pool.clear();
-        if (ctx->d_views || ctx->d_pad) {
+        if (ctx->d_views || ctx->d_pad || ctx->d_cull) {
             if (hipDeviceSynchronize() != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_views && hipFree(ctx->d_views) != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_pad && hipFree(ctx->d_pad) != hipSuccess) st = BP_ERR_DEVICE;
+            if (ctx->d_cull && hipFree(ctx->d_cull) != hipSuccess) st = BP_ERR_DEVICE;
         }
     }
     delete ctx;
     return st;
 }
 
-bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll)
+bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll, int tile_x)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (path != BP_PATH_AUTO && path != BP_PATH_PLAIN && path != BP_PATH_FUSED)
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown path");
     if (views_per_pass < 0) return fail(ctx, BP_ERR_INVALID_ARG, "views_per_pass < 0");
     if (z_unroll != 0 && !valid_zu(z_unroll)) return fail(ctx, BP_ERR_INVALID_ARG, "z_unroll not in {1,2,4,8}");
+    if (tile_x != 0 && !valid_tx(tile_x)) return fail(ctx, BP_ERR_INVALID_ARG, "tile_x not in {8,16,32,64}");
     ctx->path_override = path;
     ctx->k_override = views_per_pass;
     ctx->zu_override = z_unroll;
+    ctx->tx_override = tile_x;
     return BP_OK;
 }
 
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path* path, int* views_per_pass,
-                        int* z_unroll)
+                        int* z_unroll, int* tile_x)
 {
     if (!ctx || nx < 1 || ny < 1 || nz < 1 || n_views < 1) return BP_ERR_INVALID_ARG;
     const Plan p = plan_for(ctx, nx, ny, nz, n_views);
     if (path) *path = p.path;
     if (views_per_pass) *views_per_pass = p.k;
     if (z_unroll) *z_unroll = p.zu;
+    if (tile_x) *tile_x = p.tx;
+    return BP_OK;
+}
+
+bp_status bp_set_options(bp_ctx ctx, int options)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_NO_XCD_ORDER))
+        return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
+    ctx->options = options;
     return BP_OK;
 }
 
@@ -339,14 +364,32 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
         if (st != BP_OK) return st;
     }
 
-    if (timed(ctx, 2, s, [&] { return bp::launch_prep_views(matrices, n_views, box, ctx->d_views, s); }) !=
+    const bool column_ok = !(ctx->options & BP_OPT_NO_COLUMN);
+    if (timed(ctx, 2, s, [&] { return bp::launch_prep_views(matrices, n_views, box, column_ok, ctx->d_views, s); }) !=
         hipSuccess)
         return fail(ctx, BP_ERR_LAUNCH, "view-constant kernel launch failed");
 
+    // Clipping mask for the fused path: skip bits per (tile, view).
+    bp::Cull cull{nullptr, 0, 0};
+    if (layout != bp::Layout::Checked && !(ctx->options & BP_OPT_NO_CULL)) {
+        const int words = bp::cull_words(n_views);
+        const size_t need = (size_t)bp::n_tiles(nx, ny, nz, plan.zu, plan.tx) * (size_t)words * 4u;
+        st = ensure(ctx, &ctx->d_cull, &ctx->cull_cap, need, "clipping mask");
+        if (st != BP_OK) return st;
+        if (timed(ctx, 2, s, [&] {
+                return bp::launch_cull(ctx->d_views, n_views, box, plan.zu, plan.tx, W, H, (uint32_t*)ctx->d_cull, s);
+            }) != hipSuccess)
+            return fail(ctx, BP_ERR_LAUNCH, "clipping-mask kernel launch failed");
+        cull.bits = (const uint32_t*)ctx->d_cull;
+        cull.words = words;
+    }
+
     const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
+    const int xcd_order = (ctx->options & BP_OPT_NO_XCD_ORDER) ? 0 : 1;
     for (int k0 = 0; k0 < n_views; k0 += plan.k) {
         const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
         const void* src_views = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;
+        cull.kbase = k0;
         hipError_t e;
         if (layout != bp::Layout::Checked) {
             e = timed(ctx, 1, s, [&] {
@@ -355,11 +398,11 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             });
             if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
             e = timed(ctx, 0, s, [&] {
-                return bp::launch_backproject(dt, layout, plan.zu, volume, box, ctx->d_views + k0, kc, ctx->d_pad, W, H, s);
+                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc, ctx->d_pad, W, H, cull, xcd_order, s);
             });
         } else {
             e = timed(ctx, 0, s, [&] {
-                return bp::launch_backproject(dt, layout, plan.zu, volume, box, ctx->d_views + k0, kc, src_views, W, H, s);
+                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc, src_views, W, H, cull, xcd_order, s);
             });
         }
         if (e != hipSuccess)

@@ -10,10 +10,24 @@ namespace bp {
 // Per-view constants, one 64-byte record per view, read with scalar loads.
 struct ViewConst {
     float p[12];  // P_k row-major
-    int safe;     // 1: every voxel of the box has w >= 1e-4 * max w > 0
+    int mode;     // kModeGuarded, kModeSafe or kModeColumn
     int pad[3];
 };
 static_assert(sizeof(ViewConst) == 64, "ViewConst must be 64 bytes");
+
+// Branch of a view: guarded (some voxel of the box at w < 1e-4 max w, i.e. at
+// or behind the source), safe (every voxel in front: clamped, no tests), or
+// column (safe, and u and w do not depend on z).
+constexpr int kModeGuarded = 0, kModeSafe = 1, kModeColumn = 2;
+
+// Per-(tile, view) skip bits of a pass (null bits = no culling).
+struct Cull {
+    const uint32_t* bits;
+    int words;  // words per tile row
+    int kbase;  // bit index of the pass's first view
+};
+
+inline int cull_words(int n_views) { return (n_views + 31) / 32; }
 
 enum class Dtype : int { F32 = 0, F16 = 1, BF16 = 2 };
 
@@ -38,7 +52,8 @@ inline size_t staged_view_bytes(Layout l, int W, int H)
     return 0;
 }
 
-hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, ViewConst* out,
+// column_ok = false keeps every safe view on the general (per-voxel) branch.
+hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, bool column_ok, ViewConst* out,
                              hipStream_t s);
 
 // Copy views [0, n) of `proj` (dtype dt, H x W each) into the zero-padded
@@ -52,8 +67,22 @@ hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* o
 
 // One volume pass over views [0, n) of the given view constants; `src` is the
 // caller's images (Layout::Checked) or the staging copy of that layout.
-hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, float* vol, const Box& box,
+// tile_x: columns along x per block (64, 32, 16 or 8; the plain path and
+// the pair layout take 64 only); a block covers tile_x x (256 / tile_x)
+// columns.  xcd_order: deal contiguous z-ranges of tiles to the 8 XCDs.
+hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
-                              hipStream_t s);
+                              const Cull& cull, int xcd_order, hipStream_t s);
+
+// Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
+inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)
+{
+    const int ty = 256 / tile_x;
+    return (long)((nx + tile_x - 1) / tile_x) * ((ny + ty - 1) / ty) * ((nz + z_unroll - 1) / z_unroll);
+}
+
+// Skip bits for every (tile, view) of a call, cull_words(n_views) words per tile.
+hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_unroll, int tile_x, int W, int H,
+                       uint32_t* out, hipStream_t s);
 
 }  // namespace bp

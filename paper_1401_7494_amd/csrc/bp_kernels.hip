@@ -34,8 +34,8 @@ namespace bp {
 
 namespace {
 
-constexpr int kWaveX = 64;  // lanes along x
-constexpr int kRowsY = 4;   // waves per block, one y row each
+constexpr int kBlock = 256;  // threads per block: 4 wavefronts
+constexpr int kXcds = 8;     // MI355X: 8 XCDs, consecutive workgroups go to consecutive XCDs
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {
@@ -239,13 +239,38 @@ struct PatchSource {
         return v;
     }
 
-    __device__ __forceinline__ float patch(const View& vw, float s, float t) const
+    // Patch value at padded column c0 + fx, padded row t (t >= 0, so truncation is floor).
+    __device__ __forceinline__ float patch_at(const View& vw, int c0, float fx, float t) const
     {
-        const int c0 = (int)s, r0 = (int)t;  // s, t >= 0 here: truncation is floor
-        const float fx = __builtin_amdgcn_fractf(s);
+        const int r0 = (int)t;
         const float fy = __builtin_amdgcn_fractf(t);
         const f32x4_t q = struct_buffer_load_f32x4(vw.rs, __mul24(r0, cols()) + c0, 0, 0, 0);
         return fmaf(fx, q.y, fmaf(fy, fmaf(fx, q.w, q.z), q.x));
+    }
+
+    __device__ __forceinline__ float patch(const View& vw, float s, float t) const
+    {
+        return patch_at(vw, (int)s, __builtin_amdgcn_fractf(s), t);
+    }
+
+    // Column view (u and w do not depend on z): everything but the row is
+    // shared by the ZU voxels of the thread's column.  t(Z) = (v_xy + P[1][2] Z) / w + 1.
+    template <int ZU>
+    __device__ __forceinline__ void column(const View& vw, float uxy, float vxy, float wxy, float p12,
+                                           const float (&Z)[ZU], float (&acc)[ZU]) const
+    {
+        const float r = __builtin_amdgcn_rcpf(wxy);
+        const float s = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
+        const int c0 = (int)s;
+        const float fx = __builtin_amdgcn_fractf(s);
+        const float r2 = r * r;
+        const float dt = p12 * r;
+        const float tb = fmaf(vxy, r, 1.0f);
+#pragma unroll
+        for (int i = 0; i < ZU; ++i) {
+            const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
+            acc[i] = fmaf(patch_at(vw, c0, fx, t), r2, acc[i]);
+        }
     }
 
     // See PaddedSource::contrib_safe: positions clamped into [0, W+1] x [0, H+1].
@@ -274,13 +299,45 @@ struct PatchSource {
 // The back-projection pass.
 // ---------------------------------------------------------------------------
 
-template <class Src, int ZU, bool PADDED>
-__global__ __launch_bounds__(kWaveX* kRowsY) void backproject_kernel(
-    float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src)
+template <class Src>
+struct has_column {
+    static constexpr bool value = false;
+};
+template <>
+struct has_column<PatchSource> {
+    static constexpr bool value = true;
+};
+
+// One block = 256 threads covering a TX x (256/TX) tile of (x, y) columns and
+// ZU voxels along z; a wavefront covers TX x (64/TX) columns.  Narrow tiles
+// keep the detector footprint of one wavefront's 64 loads small.
+//
+// Tiles are numbered x fastest, then y, then z.  With xcd_order, block b
+// takes tile (b % 8) * ceil(T / 8) + b / 8, so each XCD (blocks are dealt to
+// the 8 XCDs round-robin) works through one contiguous z-range of tiles and
+// its L2 sees the detector rows of that slab only.
+//
+// cull: optional per-(tile, view) skip bits, `cull_words` words per tile,
+// bit (kbase + k) set when the whole tile projects off the detector in view k
+// of this pass.  Skipped views contribute exact zeros.
+template <class Src, int ZU, bool PADDED, int TX>
+__global__ __launch_bounds__(kBlock) void backproject_kernel(
+    float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
+    const uint32_t* __restrict__ cull, int cull_words, int kbase, int xcd_order)
 {
-    int x = (int)blockIdx.x * kWaveX + (int)threadIdx.x;
-    int y = (int)blockIdx.y * kRowsY + (int)threadIdx.y;
-    const int z0 = (int)blockIdx.z * ZU;
+    constexpr int TY = kBlock / TX;
+    const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
+    const int n_tiles = gx * gy * gz;
+    int tile = (int)blockIdx.x;
+    if (xcd_order) {
+        const int per = (n_tiles + kXcds - 1) / kXcds;
+        tile = (tile % kXcds) * per + tile / kXcds;
+    }
+    if (tile >= n_tiles) return;  // padding blocks of the XCD order (no barriers in this kernel)
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    int x = bx * TX + (int)threadIdx.x % TX;
+    int y = by * TY + (int)threadIdx.x / TX;
+    const int z0 = bz * ZU;
     const bool in_xy = (x < box.nx) & (y < box.ny);
     // Lanes past a ragged edge compute a valid voxel of the box and store nothing.
     x = min(x, box.nx - 1);
@@ -293,15 +350,26 @@ __global__ __launch_bounds__(kWaveX* kRowsY) void backproject_kernel(
         Z[i] = fmaf(box.vs, (float)min(z0 + i, box.nz - 1), box.oz);
         acc[i] = 0.0f;
     }
+    const uint32_t* cull_row = cull ? cull + (size_t)tile * cull_words : nullptr;
 
     for (int k = 0; k < n_views; ++k) {
+        if (cull_row) {
+            const int kk = kbase + k;
+            if ((cull_row[kk >> 5] >> (kk & 31)) & 1u) continue;
+        }
         const ViewConst& c = vc[k];
         const auto view = src.view(k);
         const float uxy = fmaf(c.p[1], Y, fmaf(c.p[0], X, c.p[3]));
         const float vxy = fmaf(c.p[5], Y, fmaf(c.p[4], X, c.p[7]));
         const float wxy = fmaf(c.p[9], Y, fmaf(c.p[8], X, c.p[11]));
         if constexpr (PADDED) {
-            if (c.safe) {
+            if constexpr (has_column<Src>::value) {
+                if (c.mode == kModeColumn) {
+                    src.column(view, uxy, vxy, wxy, c.p[6], Z, acc);
+                    continue;
+                }
+            }
+            if (c.mode != kModeGuarded) {
 #pragma unroll
                 for (int i = 0; i < ZU; ++i)
                     acc[i] += src.contrib_safe(view, fmaf(c.p[2], Z[i], uxy),
@@ -334,11 +402,14 @@ __global__ __launch_bounds__(kWaveX* kRowsY) void backproject_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Per-view constants: copy P_k and decide whether the view is "safe" (every
-// voxel centre of the box in front of the source by a margin).  w is affine,
-// so its extremes over the box are at the 8 corner voxels; evaluated in FP64.
+// Per-view constants: copy P_k and pick the view's branch.  w is affine, so
+// its extremes over the box are at the 8 corner voxels (evaluated in FP64).
+//   guarded  some voxel may have w < 1e-4 * max w (at or behind the source)
+//   safe     every voxel is in front of the source: clamp, no tests
+//   column   safe, and P[0][2] = P[2][2] = 0: u and w do not vary along z,
+//            as for any circular orbit about the z axis
 // ---------------------------------------------------------------------------
-__global__ void prep_views_kernel(const float* __restrict__ mats, int n_views, Box box,
+__global__ void prep_views_kernel(const float* __restrict__ mats, int n_views, Box box, int column_ok,
                                   ViewConst* __restrict__ out)
 {
     const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -358,9 +429,58 @@ __global__ void prep_views_kernel(const float* __restrict__ mats, int n_views, B
         wmin = q ? fmin(wmin, w) : w;
         wmax = q ? fmax(wmax, w) : w;
     }
-    c.safe = (wmin > 0.0 && wmin >= 1e-4 * wmax) ? 1 : 0;  // false for NaN
+    const bool safe = wmin > 0.0 && wmin >= 1e-4 * wmax;  // false for NaN
+    c.mode = !safe                                                  ? kModeGuarded
+             : (column_ok && c.p[2] == 0.0f && c.p[10] == 0.0f) ? kModeColumn
+                                                                : kModeSafe;
     c.pad[0] = c.pad[1] = c.pad[2] = 0;
     out[k] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Clipping mask (the per-line start/stop of Sec. 5, here per block tile and
+// view): bit k of a tile's row is set when all 8 corner voxels of the tile
+// project at least one pixel beyond the same detector edge (s <= -2, s >= W+1,
+// t <= -2 or t >= H+1; FP64, no division).  For a safe view w > 0 on the whole
+// box, so the tile's image is the convex hull of the corners' images and
+// every voxel of the tile clamps into the zero border: its contribution is
+// exactly 0.  Guarded views are never skipped.  One thread per (tile, word).
+// ---------------------------------------------------------------------------
+__global__ void cull_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
+                            int gx, int gy, int n_tiles, int words, int W, int H, uint32_t* __restrict__ out)
+{
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)n_tiles * words) return;
+    const int tile = (int)(id / words), word = (int)(id % words);
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    const int xs[2] = {bx * tx, min(bx * tx + tx - 1, box.nx - 1)};
+    const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
+    const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
+    double cx[2], cy[2], cz[2];
+    for (int i = 0; i < 2; ++i) {
+        cx[i] = (double)box.ox + (double)box.vs * xs[i];
+        cy[i] = (double)box.oy + (double)box.vs * ys[i];
+        cz[i] = (double)box.oz + (double)box.vs * zs[i];
+    }
+    uint32_t bits = 0;
+    const int k_end = min(n_views, (word + 1) * 32);
+    for (int k = word * 32; k < k_end; ++k) {
+        const ViewConst& c = vc[k];
+        if (c.mode == kModeGuarded) continue;
+        bool left = true, right = true, top = true, bottom = true;
+        for (int q = 0; q < 8; ++q) {
+            const double X = cx[q & 1], Y = cy[(q >> 1) & 1], Z = cz[q >> 2];
+            const double u = (double)c.p[0] * X + (double)c.p[1] * Y + (double)c.p[2] * Z + (double)c.p[3];
+            const double v = (double)c.p[4] * X + (double)c.p[5] * Y + (double)c.p[6] * Z + (double)c.p[7];
+            const double w = (double)c.p[8] * X + (double)c.p[9] * Y + (double)c.p[10] * Z + (double)c.p[11];
+            left &= u <= -2.0 * w;
+            right &= u >= (W + 1.0) * w;
+            top &= v <= -2.0 * w;
+            bottom &= v >= (H + 1.0) * w;
+        }
+        if (left | right | top | bottom) bits |= 1u << (k & 31);
+    }
+    out[id] = bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -426,32 +546,37 @@ __global__ __launch_bounds__(256) void patch_kernel(const T* __restrict__ proj, 
     out[((size_t)k * Hq + r) * Wq + c] = q;
 }
 
-template <class Src, bool PADDED>
+template <class Src, bool PADDED, int TX>
 hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, int n, const Src& src,
-                     hipStream_t s)
+                     const Cull& cl, int xcd_order, hipStream_t s)
 {
-    const dim3 block(kWaveX, kRowsY, 1);
+    const dim3 block(kBlock, 1, 1);
     auto grid = [&](int z) {
-        return dim3((unsigned)((box.nx + kWaveX - 1) / kWaveX), (unsigned)((box.ny + kRowsY - 1) / kRowsY),
-                    (unsigned)((box.nz + z - 1) / z));
+        const long t = n_tiles(box.nx, box.ny, box.nz, z, TX);
+        return dim3((unsigned)(xcd_order ? (t + kXcds - 1) / kXcds * kXcds : t));
     };
+#define BP_LAUNCH(Z)                                                                                         \
+    hipLaunchKernelGGL((backproject_kernel<Src, Z, PADDED, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, \
+                       cl.bits, cl.words, cl.kbase, xcd_order)
     switch (zu) {
-    case 1: hipLaunchKernelGGL((backproject_kernel<Src, 1, PADDED>), grid(1), block, 0, s, vol, box, vc, n, src); break;
-    case 2: hipLaunchKernelGGL((backproject_kernel<Src, 2, PADDED>), grid(2), block, 0, s, vol, box, vc, n, src); break;
-    case 4: hipLaunchKernelGGL((backproject_kernel<Src, 4, PADDED>), grid(4), block, 0, s, vol, box, vc, n, src); break;
-    case 8: hipLaunchKernelGGL((backproject_kernel<Src, 8, PADDED>), grid(8), block, 0, s, vol, box, vc, n, src); break;
+    case 1: BP_LAUNCH(1); break;
+    case 2: BP_LAUNCH(2); break;
+    case 4: BP_LAUNCH(4); break;
+    case 8: BP_LAUNCH(8); break;
     default: return hipErrorInvalidValue;
     }
+#undef BP_LAUNCH
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, ViewConst* out, hipStream_t s)
+hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, bool column_ok, ViewConst* out,
+                             hipStream_t s)
 {
     const int threads = 64;
     hipLaunchKernelGGL(prep_views_kernel, dim3((unsigned)((n_views + threads - 1) / threads)), dim3(threads), 0,
-                       s, mats, n_views, box, out);
+                       s, mats, n_views, box, column_ok ? 1 : 0, out);
     return hipGetLastError();
 }
 
@@ -481,22 +606,47 @@ hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* o
     return hipGetLastError();
 }
 
-hipError_t launch_backproject(Dtype dt, Layout layout, int zu, float* vol, const Box& box, const ViewConst* vc,
-                              int n, const void* src, int W, int H, hipStream_t s)
+hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_unroll, int tile_x, int W, int H,
+                       uint32_t* out, hipStream_t s)
+{
+    const int tx = tile_x, ty = kBlock / tile_x;
+    const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
+    const long tiles = n_tiles(box.nx, box.ny, box.nz, z_unroll, tile_x);
+    const int words = cull_words(n_views);
+    const long total = tiles * words;
+    const int threads = 256;
+    hipLaunchKernelGGL(cull_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
+                       n_views, box, tx, ty, z_unroll, gx, gy, (int)tiles, words, W, H, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
+                              const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
+                              int xcd_order, hipStream_t s)
 {
     const uint8_t* base = (const uint8_t*)src;
-    if (layout == Layout::Patch) return launch_zu<PatchSource, true>(zu, vol, box, vc, n, {base, W, H}, s);
+    if (layout == Layout::Patch) {
+        const PatchSource ps{base, W, H};
+        switch (tile_x) {
+        case 64: return launch_zu<PatchSource, true, 64>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 32: return launch_zu<PatchSource, true, 32>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 16: return launch_zu<PatchSource, true, 16>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 8: return launch_zu<PatchSource, true, 8>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (tile_x != 64) return hipErrorInvalidValue;
     if (layout == Layout::Pairs) {
         switch (dt) {
-        case Dtype::F32: return launch_zu<PaddedSource<Dtype::F32>, true>(zu, vol, box, vc, n, {base, W, H}, s);
-        case Dtype::F16: return launch_zu<PaddedSource<Dtype::F16>, true>(zu, vol, box, vc, n, {base, W, H}, s);
-        case Dtype::BF16: return launch_zu<PaddedSource<Dtype::BF16>, true>(zu, vol, box, vc, n, {base, W, H}, s);
+        case Dtype::F32: return launch_zu<PaddedSource<Dtype::F32>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
+        case Dtype::F16: return launch_zu<PaddedSource<Dtype::F16>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
+        case Dtype::BF16: return launch_zu<PaddedSource<Dtype::BF16>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
         }
     } else {
         switch (dt) {
-        case Dtype::F32: return launch_zu<CheckedSource<float>, false>(zu, vol, box, vc, n, {base, W, H}, s);
-        case Dtype::F16: return launch_zu<CheckedSource<__half>, false>(zu, vol, box, vc, n, {base, W, H}, s);
-        case Dtype::BF16: return launch_zu<CheckedSource<uint16_t>, false>(zu, vol, box, vc, n, {base, W, H}, s);
+        case Dtype::F32: return launch_zu<CheckedSource<float>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
+        case Dtype::F16: return launch_zu<CheckedSource<__half>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
+        case Dtype::BF16: return launch_zu<CheckedSource<uint16_t>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
         }
     }
     return hipErrorInvalidValue;

@@ -45,7 +45,7 @@ def product_matrices(scanner):
 
 
 def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0, zu=0, init=None,
-            stream=None):
+            stream=None, tx=0):
     """Back project on cuda:0 through the C ABI; returns the volume as a float32 numpy array."""
     dev = torch.device("cuda:0")
     nz, ny, nx = shape
@@ -55,7 +55,7 @@ def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0,
     m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
     H, W = p.shape[1:]
     with bp.Context(W, H, dtype) as ctx:
-        ctx.set_tuning(path, k, zu)
+        ctx.set_tuning(path, k, zu, tx)
         ctx.backproject(vol, p, m, voxel_size, origin, stream)
         torch.cuda.synchronize()
     return vol.cpu().numpy()

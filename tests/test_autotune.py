@@ -9,6 +9,8 @@ def test_candidates_cover_the_required_views_per_pass():
     ks = {c.views_per_pass for c in cands if c.path == "fused"}
     assert {1, 2, 4, 8, 16} <= ks
     assert {c.z_unroll for c in cands} == {1, 2, 4, 8}
+    assert {c.tile_x for c in cands if c.path == "fused"} == {8, 16, 32, 64}
+    assert all(c.tile_x == 64 for c in cands if c.path == "plain")
     small = at.candidates(at.Problem(64, 64, 2, 3, "f32", 64, 64))
     assert all(c.z_unroll <= 2 and c.views_per_pass <= 3 for c in small)
 
@@ -18,22 +20,22 @@ def test_search_picks_the_fastest_by_median():
 
     def fake(c):
         calls[c] = calls.get(c, 0) + 1
-        base = 100.0 / c.views_per_pass + 10.0 / c.z_unroll + (50 if c.path == "plain" else 0)
+        base = 100.0 / c.views_per_pass + 10.0 / c.z_unroll + (50 if c.path == "plain" else 0) + abs(c.tile_x - 16)
         # one noisy outlier per candidate must not move the median
         return base * (5.0 if calls[c] == 2 else 1.0)
 
     r = at.search(P, fake, reps=3, warmup=1)
-    assert r.best == at.Candidate("fused", 64, 8)
+    assert r.best == at.Candidate("fused", 64, 8, 16)
     assert all(v == 4 for v in calls.values())  # 1 warm-up + 3 timed
     assert len(r.timings_ms) == len(at.candidates(P))
 
 
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "cache.json")
-    r = at.Result(at.Candidate("fused", 16, 4), {"fused/16/4": 1.0})
+    r = at.Result(at.Candidate("fused", 16, 4, 8), {"fused/16/4/8": 1.0})
     key = P.key("AMD Instinct MI355X")
     assert at.lookup(key, path) is None
     at.store(key, r, path)
-    assert at.lookup(key, path) == at.Candidate("fused", 16, 4)
+    assert at.lookup(key, path) == at.Candidate("fused", 16, 4, 8)
     at.store(P.key("other"), at.Result(at.Candidate("plain", 1, 8)), path)
-    assert at.lookup(key, path) == at.Candidate("fused", 16, 4)
+    assert at.lookup(key, path) == at.Candidate("fused", 16, 4, 8)

@@ -175,8 +175,10 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_backproject(h, args["v"], args["p"], args["m"], 2, 4, 1.0, bad, None) == bp.BP_ERR_INVALID_ARG
         assert L.bp_backproject(h, args["v"] + 2, args["p"], args["m"], 2, 4, 1.0, o, None) == bp.BP_ERR_INVALID_ARG
         assert L.bp_backproject(h, args["v"], args["p"], args["m"], 2, 2000, 1.0, o, None) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_tuning(h, 9, 0, 0) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_tuning(h, 0, 0, 3) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_tuning(h, 9, 0, 0, 0) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_tuning(h, 0, 0, 3, 0) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 64) == bp.BP_ERR_INVALID_ARG
         torch.cuda.synchronize()
     assert not vol.any()
 
@@ -193,11 +195,12 @@ def test_plan_reports_choices():
     with bp.Context(1248, 960, "f32") as ctx:
         p = ctx.plan(512, 512, 512, 496)
         assert p.path in ("plain", "fused") and p.z_unroll in (1, 2, 4, 8)
-        ctx.set_tuning("plain", 0, 4)
+        ctx.set_tuning("plain", 0, 4, 16)
         p = ctx.plan(512, 512, 512, 496)
-        assert (p.path, p.views_per_pass, p.z_unroll) == ("plain", 1, 4)
-        ctx.set_tuning("fused", 500, 2)
-        assert ctx.plan(64, 64, 64, 496).views_per_pass == 496
+        assert (p.path, p.views_per_pass, p.z_unroll, p.tile_x) == ("plain", 1, 4, 64)
+        ctx.set_tuning("fused", 500, 2, 8)
+        p = ctx.plan(64, 64, 64, 496)
+        assert (p.views_per_pass, p.tile_x) == (496, 8)
 
 
 # ---------------------------------------------------------------------------
@@ -259,3 +262,65 @@ def test_parity_l512_sampled(dtype):
         print(f"L=512 {dtype} block {name}: rms error / volume rms = {rel_vol:.3e}, "
               f"own rel-L2 {gc.rel_l2(got[z0:z1, y0:y1, x0:x1], ref):.3e}")
         assert rel_vol <= gc.REL_L2_TOL, (name, rel_vol)
+
+
+def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
+              no_xcd_order=False):
+    dev = torch.device("cuda:0")
+    vol = torch.zeros(shape, dtype=torch.float32, device=dev)
+    p = proj.to(dev).contiguous()
+    m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
+    n, H, W = p.shape
+    with bp.Context(W, H, dtype) as ctx:
+        ctx.set_tuning("fused", k, zu, tx)
+        ctx.set_options(no_cull=no_cull, no_column=no_column, no_xcd_order=no_xcd_order)
+        ctx.backproject(vol, p, m, vs, origin)
+        torch.cuda.synchronize()
+    return vol.cpu().numpy()
+
+
+@pytest.mark.parametrize("zu", [1, 8])
+def test_clipping_mask_is_exact_and_column_path_matches(zu):
+    """Skipping tiles that project off the detector changes no bit; the column branch
+    (u, w constant along z) and the general branch both match the oracle."""
+    sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)  # small detector: many tiles fall off it
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(77))
+    P32 = gc.product_matrices(sc)
+    shape, vs = (40, 70, 130), 2.0
+    origin = _box_origin(shape, vs)
+    full = _run_opts(proj, P32, shape, vs, origin, no_cull=True, k=13, zu=zu)
+    culled = _run_opts(proj, P32, shape, vs, origin, k=13, zu=zu)
+    assert np.array_equal(culled, full)
+    general = _run_opts(proj, P32, shape, vs, origin, no_column=True, k=13, zu=zu)
+    ref = _oracle_box(proj, P32, shape, vs, origin)
+    for name, got in (("column", culled), ("general", general)):
+        err = gc.error_stats(got, ref)
+        print(f"\n{name} ZU={zu}: {err}")
+        assert err["rel_l2"] <= gc.REL_L2_TOL, (name, err)
+
+
+def test_column_branch_needs_exact_zeros():
+    """A matrix with a tiny P[0][2] takes the general branch; results still match the oracle."""
+    sc = synth.Scanner(n_views=7, W=96, H=72, pitch=3.0)
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(5))
+    P32 = gc.product_matrices(sc).copy()
+    P32[:, 0, 2] = 1e-3  # a tilted detector column axis
+    origin = _box_origin(BOX, VS)
+    got = _run_opts(proj, P32, BOX, VS, origin, k=4, zu=8)
+    ref = _oracle_box(proj, P32, BOX, VS, origin)
+    assert gc.rel_l2(got, ref) <= gc.REL_L2_TOL
+
+
+@pytest.mark.parametrize("tx", [8, 16, 32, 64])
+@pytest.mark.parametrize("zu", [1, 4, 8])
+def test_tile_shapes_and_block_order(small_inputs, tx, zu):
+    """Every block tile shape covers the ragged box exactly once; the XCD tile order
+    changes no bit; culling stays exact for every shape."""
+    proj32, P32 = small_inputs
+    origin = _box_origin(BOX, VS)
+    a = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx)
+    b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_xcd_order=True)
+    c = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_cull=True)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    ref = _oracle_box(proj32, P32, BOX, VS, origin)
+    assert gc.rel_l2(a, ref) <= gc.REL_L2_TOL

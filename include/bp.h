@@ -128,18 +128,25 @@ bp_status bp_backproject_box(bp_ctx ctx, float *volume, int nx, int ny, int nz,
 bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll, int tile_x);
 
 /*
- * Options (bit flags, default 0 = all optimisations on; results are equal
- * either way, up to FP32 rounding for BP_OPT_NO_COLUMN):
+ * Options (bit flags, default 0; results are equal whatever the flags, up to
+ * FP32 rounding for BP_OPT_NO_COLUMN and FP16 rounding for BP_OPT_WIDE_STAGING):
  *   BP_OPT_NO_CULL    do not skip (tile, view) pairs whose whole tile projects
  *                     off the detector (the clipping mask of Sec. 5)
  *   BP_OPT_NO_COLUMN  do not specialise views whose matrix has P[0][2] = P[2][2] = 0
  *                     (u and w constant along z, as for a circular orbit about z)
- *   BP_OPT_NO_XCD_ORDER  number blocks in plain tile order instead of dealing
- *                     contiguous z-ranges of tiles to the 8 XCDs
+ *   BP_OPT_WIDE_STAGING  stage FP16/BF16 projections as FP32 bilinear-patch
+ *                     coefficients (16 bytes per pixel) instead of the default
+ *                     compact FP16 coefficients (8 bytes, scaled per view by a
+ *                     power of two; adds the rounding of the pixel differences
+ *                     to FP16, ~2^-11 relative)
+ *   BP_OPT_XCD_ORDER  deal contiguous z-ranges of tiles to the 8 XCDs instead of
+ *                     the default plain tile order (x fastest; measured faster on
+ *                     MI355X, where all XCDs then share one detector-row band in MALL)
  */
 #define BP_OPT_NO_CULL 1
 #define BP_OPT_NO_COLUMN 2
-#define BP_OPT_NO_XCD_ORDER 4
+#define BP_OPT_XCD_ORDER 4
+#define BP_OPT_WIDE_STAGING 8
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */

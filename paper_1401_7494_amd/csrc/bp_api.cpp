@@ -25,6 +25,8 @@ struct bp_ctx_s {
     size_t pad_cap = 0;  // bytes
     void* d_cull = nullptr;
     size_t cull_cap = 0;  // bytes
+    void* d_scale = nullptr;  // compact staging: per-view max |pixel| bits, then 2^-e scales
+    size_t scale_cap = 0;
     int options = 0;      // BP_OPT_* flags
     // overrides set by bp_set_tuning (0 = tuned)
     bp_path path_override = BP_PATH_AUTO;
@@ -253,11 +255,12 @@ bp_status bp_destroy(bp_ctx ctx)
         if (drain_timing(ctx) != BP_OK) st = BP_ERR_DEVICE;
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
         ctx->event_pool.clear();
-        if (ctx->d_views || ctx->d_pad || ctx->d_cull) {
+        if (ctx->d_views || ctx->d_pad || ctx->d_cull || ctx->d_scale) {
             if (hipDeviceSynchronize() != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_views && hipFree(ctx->d_views) != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_pad && hipFree(ctx->d_pad) != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_cull && hipFree(ctx->d_cull) != hipSuccess) st = BP_ERR_DEVICE;
+            if (ctx->d_scale && hipFree(ctx->d_scale) != hipSuccess) st = BP_ERR_DEVICE;
         }
     }
     delete ctx;
@@ -294,7 +297,7 @@ bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path
 bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
-    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_NO_XCD_ORDER))
+    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     ctx->options = options;
     return BP_OK;
@@ -357,11 +360,17 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                           sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
     if (st != BP_OK) return st;
     if (ctx->views_cap < sizeof(bp::ViewConst) * (size_t)n_views) return BP_ERR_OUT_OF_MEMORY;
-    const bp::Layout layout = plan.path == BP_PATH_FUSED ? ctx->fused_layout : bp::Layout::Checked;
+    bp::Layout layout = plan.path == BP_PATH_FUSED ? ctx->fused_layout : bp::Layout::Checked;
+    if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
+        layout = bp::Layout::Patch16;
     if (layout != bp::Layout::Checked) {
         st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, bp::staged_view_bytes(layout, W, H) * (size_t)plan.k,
                     "staged projections");
         if (st != BP_OK) return st;
+        if (layout == bp::Layout::Patch16) {
+            st = ensure(ctx, &ctx->d_scale, &ctx->scale_cap, 8u * (size_t)plan.k, "staging scales");
+            if (st != BP_OK) return st;
+        }
     }
 
     const bool column_ok = !(ctx->options & BP_OPT_NO_COLUMN);
@@ -385,24 +394,32 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     }
 
     const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
-    const int xcd_order = (ctx->options & BP_OPT_NO_XCD_ORDER) ? 0 : 1;
+    const int xcd_order = (ctx->options & BP_OPT_XCD_ORDER) ? 1 : 0;
     for (int k0 = 0; k0 < n_views; k0 += plan.k) {
         const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
         const void* src_views = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;
         cull.kbase = k0;
         hipError_t e;
         if (layout != bp::Layout::Checked) {
+            uint32_t* maxabs = (uint32_t*)ctx->d_scale;
+            float* inv_scale = ctx->d_scale ? (float*)ctx->d_scale + plan.k : nullptr;
             e = timed(ctx, 1, s, [&] {
-                return layout == bp::Layout::Patch ? bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s)
-                                                   : bp::launch_pad(dt, src_views, W, H, kc, ctx->d_pad, s);
+                switch (layout) {
+                case bp::Layout::Patch: return bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s);
+                case bp::Layout::Patch16:
+                    return bp::launch_patch16(dt, src_views, W, H, kc, ctx->d_pad, maxabs, inv_scale, s);
+                default: return bp::launch_pad(dt, src_views, W, H, kc, ctx->d_pad, s);
+                }
             });
             if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
             e = timed(ctx, 0, s, [&] {
-                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc, ctx->d_pad, W, H, cull, xcd_order, s);
+                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
+                                              ctx->d_pad, W, H, cull, xcd_order, inv_scale, s);
             });
         } else {
             e = timed(ctx, 0, s, [&] {
-                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc, src_views, W, H, cull, xcd_order, s);
+                return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
+                                              src_views, W, H, cull, xcd_order, nullptr, s);
             });
         }
         if (e != hipSuccess)

@@ -35,7 +35,8 @@ enum class Dtype : int { F32 = 0, F16 = 1, BF16 = 2 };
 enum class Layout : int {
     Checked = 0,  // the caller's images, per-tap detector bounds (plain path)
     Pairs = 1,    // zero-padded staging copy, 4-byte elements (FP32 pixel or 16-bit pair)
-    Patch = 2     // bilinear-patch staging copy, 16-byte FP32 coefficients per element
+    Patch = 2,    // bilinear-patch staging copy, 16-byte FP32 coefficients per element
+    Patch16 = 3   // bilinear-patch staging copy, 8-byte scaled FP16 coefficients per element
 };
 
 struct Box {
@@ -48,6 +49,7 @@ struct Box {
 inline size_t staged_view_bytes(Layout l, int W, int H)
 {
     if (l == Layout::Patch) return (size_t)(W + 2) * (size_t)(H + 2) * 16u;
+    if (l == Layout::Patch16) return (size_t)(W + 2) * (size_t)(H + 2) * 8u;
     if (l == Layout::Pairs) return (size_t)(W + 3) * (size_t)(H + 3) * 4u;
     return 0;
 }
@@ -65,6 +67,11 @@ hipError_t launch_pad(Dtype dt, const void* proj, int W, int H, int n, void* pad
 // Bilinear-patch staging copy of views [0, n) of `proj`.
 hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, hipStream_t s);
 
+// Compact (FP16, scaled) bilinear-patch staging of views [0, n): per-view
+// max |pixel| into maxabs[n] (scratch), 2^-e scale into inv_scale[n].
+hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void* out, uint32_t* maxabs,
+                          float* inv_scale, hipStream_t s);
+
 // One volume pass over views [0, n) of the given view constants; `src` is the
 // caller's images (Layout::Checked) or the staging copy of that layout.
 // tile_x: columns along x per block (64, 32, 16 or 8; the plain path and
@@ -72,7 +79,7 @@ hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* o
 // columns.  xcd_order: deal contiguous z-ranges of tiles to the 8 XCDs.
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
-                              const Cull& cull, int xcd_order, hipStream_t s);
+                              const Cull& cull, int xcd_order, const float* inv_scale, hipStream_t s);
 
 // Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
 inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)

@@ -295,6 +295,94 @@ struct PatchSource {
     }
 };
 
+// Compact bilinear-patch layout for 16-bit projections: the same four
+// coefficients as PatchSource, stored as FP16 (8 bytes per record) after
+// scaling view k by a power of two, 2^e_k, chosen from the view's largest
+// |pixel| so that no coefficient can overflow FP16 (|dxy| <= 4 max|p| <=
+// 2^13).  v_fma_mix_f32 evaluates FP16 coefficients with FP32 weights and
+// FP32 results, so Part 3 still costs three instructions; the scale is undone
+// in the 1/w^2 weight (exact: a power of two).
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+__device__ f16x4_t struct_buffer_load_f16x4(i32x4_t rsrc, int vindex, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v4f16");
+
+struct Patch16Source {
+    const uint8_t* base;
+    int W, H;
+    const float* inv_scale;  // 2^-e_k per view of the pass
+
+    struct View {
+        i32x4_t rs;
+        float inv;
+    };
+
+    __device__ __forceinline__ int cols() const { return W + 2; }
+
+    __device__ __forceinline__ View view(int k) const
+    {
+        const uint32_t n = (uint32_t)(W + 2) * (uint32_t)(H + 2);
+        const uint64_t a = (uint64_t)(base + (size_t)k * n * 8u);
+        View v;
+        v.rs.x = (int)(uint32_t)a;
+        v.rs.y = (int)((uint32_t)(a >> 32) & 0xffffu) | (8 << 16);  // stride 8 bytes
+        v.rs.z = (int)n;
+        v.rs.w = 0x00020000;
+        v.inv = inv_scale[k];
+        return v;
+    }
+
+    __device__ __forceinline__ float patch_at(const View& vw, int c0, float fx, float t) const
+    {
+        const int r0 = (int)t;
+        const float fy = __builtin_amdgcn_fractf(t);
+        const f16x4_t q = struct_buffer_load_f16x4(vw.rs, __mul24(r0, cols()) + c0, 0, 0, 0);
+        return fmaf(fx, (float)q.y, fmaf(fy, fmaf(fx, (float)q.w, (float)q.z), (float)q.x));
+    }
+
+    __device__ __forceinline__ float patch(const View& vw, float s, float t) const
+    {
+        return patch_at(vw, (int)s, __builtin_amdgcn_fractf(s), t);
+    }
+
+    template <int ZU>
+    __device__ __forceinline__ void column(const View& vw, float uxy, float vxy, float wxy, float p12,
+                                           const float (&Z)[ZU], float (&acc)[ZU]) const
+    {
+        const float r = __builtin_amdgcn_rcpf(wxy);
+        const float s = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
+        const int c0 = (int)s;
+        const float fx = __builtin_amdgcn_fractf(s);
+        const float r2 = r * r * vw.inv;
+        const float dt = p12 * r;
+        const float tb = fmaf(vxy, r, 1.0f);
+#pragma unroll
+        for (int i = 0; i < ZU; ++i) {
+            const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
+            acc[i] = fmaf(patch_at(vw, c0, fx, t), r2, acc[i]);
+        }
+    }
+
+    __device__ __forceinline__ float contrib_safe(const View& vw, float u, float v, float w) const
+    {
+        const float r = __builtin_amdgcn_rcpf(w);
+        const float s = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
+        const float t = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
+        return patch(vw, s, t) * (r * (r * vw.inv));
+    }
+
+    __device__ __forceinline__ float contrib_guarded(const View& vw, float u, float v, float w) const
+    {
+        const float r = __builtin_amdgcn_rcpf(w);
+        float s = fmaf(u, r, 1.0f), t = fmaf(v, r, 1.0f);
+        const bool ok = (w > 0.0f) & (s > 0.0f) & (s < (float)(W + 1)) & (t > 0.0f) &
+                        (t < (float)(H + 1));
+        s = ok ? s : 0.0f;
+        t = ok ? t : 0.0f;
+        const float val = patch(vw, s, t);
+        return ok ? val * (r * (r * vw.inv)) : 0.0f;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // The back-projection pass.
 // ---------------------------------------------------------------------------
@@ -307,15 +395,21 @@ template <>
 struct has_column<PatchSource> {
     static constexpr bool value = true;
 };
+template <>
+struct has_column<Patch16Source> {
+    static constexpr bool value = true;
+};
 
 // One block = 256 threads covering a TX x (256/TX) tile of (x, y) columns and
 // ZU voxels along z; a wavefront covers TX x (64/TX) columns.  Narrow tiles
 // keep the detector footprint of one wavefront's 64 loads small.
 //
-// Tiles are numbered x fastest, then y, then z.  With xcd_order, block b
-// takes tile (b % 8) * ceil(T / 8) + b / 8, so each XCD (blocks are dealt to
-// the 8 XCDs round-robin) works through one contiguous z-range of tiles and
-// its L2 sees the detector rows of that slab only.
+// Tiles are numbered x fastest, then y, then z, and by default block b takes
+// tile b: the blocks resident at any moment cover a thin z-band of the whole
+// xy-plane, whose projection is a band of detector rows shared by all XCDs in
+// MALL.  With xcd_order, block b takes tile (b % 8) * ceil(T / 8) + b / 8, so
+// each XCD (blocks are dealt to the 8 XCDs round-robin) works through its own
+// contiguous z-range; on MI355X that is slower (8 bands compete for MALL).
 //
 // cull: optional per-(tile, view) skip bits, `cull_words` words per tile,
 // bit (kbase + k) set when the whole tile projects off the detector in view k
@@ -546,6 +640,65 @@ __global__ __launch_bounds__(256) void patch_kernel(const T* __restrict__ proj, 
     out[((size_t)k * Hq + r) * Wq + c] = q;
 }
 
+// Largest |pixel| of each view (as the bits of a non-negative float, which
+// order like unsigned integers): block reduction, then one atomic per block.
+template <typename T>
+__global__ __launch_bounds__(256) void maxabs_kernel(const T* __restrict__ proj, int W, int H,
+                                                     uint32_t* __restrict__ out)
+{
+    const int k = (int)blockIdx.y;
+    const size_t n = (size_t)W * H;
+    const T* img = proj + (size_t)k * n;
+    float m = 0.0f;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(pixel_f32(img, W, H, (int)(i % W), (int)(i / W))));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    __shared__ float part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+        atomicMax(&out[k], __float_as_uint(m));
+    }
+}
+
+// 2^e with 4 * maxabs * 2^e <= 2^15 (so |coefficient| <= 2^15 < 65504); 1 for a zero view.
+__device__ __forceinline__ float patch16_scale(uint32_t maxabs_bits)
+{
+    const float m = __uint_as_float(maxabs_bits);
+    if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
+    int e;
+    frexpf(m, &e);  // m < 2^e
+    return ldexpf(1.0f, 13 - e);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void patch16_kernel(const T* __restrict__ proj, int W, int H,
+                                                      const uint32_t* __restrict__ maxabs,
+                                                      f16x4_t* __restrict__ out, float* __restrict__ inv_scale)
+{
+    const int Wq = W + 2, Hq = H + 2;
+    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int r = (int)blockIdx.y;
+    const int k = (int)blockIdx.z;
+    const float sc = patch16_scale(maxabs[k]);
+    if (c == 0 && r == 0) inv_scale[k] = 1.0f / sc;
+    if (c >= Wq || r >= Hq) return;
+    const T* img = proj + (size_t)k * W * H;
+    const int i = c - 1, j = r - 1;
+    const float a = pixel_f32(img, W, H, i, j) * sc;
+    const float b = pixel_f32(img, W, H, i + 1, j) * sc;
+    const float cc = pixel_f32(img, W, H, i, j + 1) * sc;
+    const float d = pixel_f32(img, W, H, i + 1, j + 1) * sc;
+    const float dx = b - a;
+    f16x4_t q;
+    q.x = (_Float16)a;
+    q.y = (_Float16)dx;
+    q.z = (_Float16)(cc - a);
+    q.w = (_Float16)((d - cc) - dx);
+    out[((size_t)k * Hq + r) * Wq + c] = q;
+}
+
 template <class Src, bool PADDED, int TX>
 hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, int n, const Src& src,
                      const Cull& cl, int xcd_order, hipStream_t s)
@@ -620,11 +773,47 @@ hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_u
     return hipGetLastError();
 }
 
+hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void* out, uint32_t* maxabs,
+                          float* inv_scale, hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(maxabs, 0, sizeof(uint32_t) * (size_t)n, s);
+    if (e != hipSuccess) return e;
+    const dim3 rgrid(64, (unsigned)n), block(256, 1, 1);
+    const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)(H + 2), (unsigned)n);
+    f16x4_t* q = (f16x4_t*)out;
+    switch (dt) {
+    case Dtype::F32:
+        hipLaunchKernelGGL(maxabs_kernel<float>, rgrid, block, 0, s, (const float*)proj, W, H, maxabs);
+        hipLaunchKernelGGL(patch16_kernel<float>, grid, block, 0, s, (const float*)proj, W, H, maxabs, q, inv_scale);
+        break;
+    case Dtype::F16:
+        hipLaunchKernelGGL(maxabs_kernel<__half>, rgrid, block, 0, s, (const __half*)proj, W, H, maxabs);
+        hipLaunchKernelGGL(patch16_kernel<__half>, grid, block, 0, s, (const __half*)proj, W, H, maxabs, q, inv_scale);
+        break;
+    case Dtype::BF16:
+        hipLaunchKernelGGL(maxabs_kernel<uint16_t>, rgrid, block, 0, s, (const uint16_t*)proj, W, H, maxabs);
+        hipLaunchKernelGGL(patch16_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)proj, W, H, maxabs, q,
+                           inv_scale);
+        break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
-                              int xcd_order, hipStream_t s)
+                              int xcd_order, const float* inv_scale, hipStream_t s)
 {
     const uint8_t* base = (const uint8_t*)src;
+    if (layout == Layout::Patch16) {
+        const Patch16Source ps{base, W, H, inv_scale};
+        switch (tile_x) {
+        case 64: return launch_zu<Patch16Source, true, 64>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 32: return launch_zu<Patch16Source, true, 32>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 16: return launch_zu<Patch16Source, true, 16>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        case 8: return launch_zu<Patch16Source, true, 8>(zu, vol, box, vc, n, ps, cl, xcd_order, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (layout == Layout::Patch) {
         const PatchSource ps{base, W, H};
         switch (tile_x) {

@@ -1,0 +1,240 @@
+"""Serving loop: continuous batching of reconstruction requests on one GPU.
+
+Requests (volume edge L, number of views, storage dtype, phantom seed) arrive
+over time.  The server keeps a FIFO of arrived requests and admits the oldest
+ones that fit -- in both the HBM budget (volume + projections + library
+scratch) and the in-flight limit -- whenever a slot and memory free up, not
+in fixed batches.  Every admitted request gets its own HIP stream and library
+context, so the back projections of different requests overlap on the device;
+a request whose inputs are still being made does not hold up the others.
+Latency is measured from arrival to the volume being ready.
+
+The executor does the device work; ``FakeExecutor`` stands in for it with
+simulated durations so the scheduling logic is testable on the CPU.
+"""
+from __future__ import annotations
+
+import heapq
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import synth
+
+GIB = 1 << 30
+
+
+@dataclass
+class Completed:
+    rid: int
+    arrival_s: float
+    admitted_s: float
+    done_s: float
+    updates: float
+    footprint: int
+    result: object = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+    @property
+    def queue_s(self) -> float:
+        return self.admitted_s - self.arrival_s
+
+
+@dataclass
+class Report:
+    completed: list
+    makespan_s: float
+    peak_bytes: int
+    peak_inflight: int
+    rejected: list = field(default_factory=list)
+
+    def latencies(self):
+        return np.array([c.latency_s for c in self.completed])
+
+    def summary(self) -> dict:
+        lat = self.latencies()
+        upd = sum(c.updates for c in self.completed)
+        return {
+            "requests": len(self.completed),
+            "rejected": len(self.rejected),
+            "p50_latency_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+            "mean_queue_ms": float(np.mean([c.queue_s for c in self.completed]) * 1e3) if len(lat) else None,
+            "aggregate_gups": float(upd / self.makespan_s / 1e9) if self.makespan_s > 0 else None,
+            "makespan_s": self.makespan_s,
+            "peak_hbm_gib": self.peak_bytes / GIB,
+            "peak_inflight": self.peak_inflight,
+        }
+
+
+class Server:
+    """Admission by HBM budget and in-flight limit, FIFO among arrived requests."""
+
+    def __init__(self, executor, budget_bytes: int, max_inflight: int = 8, clock=time.perf_counter,
+                 sleep=time.sleep, poll_s: float = 2e-4):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_inflight = int(max_inflight)
+        self.clock = clock
+        self.sleep = sleep
+        self.poll_s = poll_s
+
+    def run(self, requests) -> Report:
+        pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
+        waiting = []  # arrived, not admitted (FIFO)
+        inflight = {}  # rid -> (handle, request, footprint, admitted_s)
+        used = peak = peak_n = 0
+        done, rejected = [], []
+        t0 = self.clock()
+        i = 0
+        while i < len(pending) or waiting or inflight:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival_s <= now:
+                r = pending[i]
+                i += 1
+                if self.ex.footprint(r) > self.budget:
+                    rejected.append(r)  # can never fit
+                else:
+                    waiting.append(r)
+            progressed = False
+            # completions free memory and slots
+            for rid in list(inflight):
+                h, r, fp, adm = inflight[rid]
+                if self.ex.poll(h):
+                    res = self.ex.finish(h)
+                    done.append(Completed(r.rid, r.arrival_s, adm, self.clock() - t0, self.ex.updates(r), fp, res))
+                    used -= fp
+                    del inflight[rid]
+                    progressed = True
+            # admit the oldest arrived requests that fit (a large one does not block smaller ones behind it)
+            for r in list(waiting):
+                if len(inflight) >= self.max_inflight:
+                    break
+                fp = self.ex.footprint(r)
+                if used + fp <= self.budget:
+                    waiting.remove(r)
+                    adm = self.clock() - t0
+                    inflight[r.rid] = (self.ex.start(r), r, fp, adm)
+                    used += fp
+                    peak = max(peak, used)
+                    peak_n = max(peak_n, len(inflight))
+                    progressed = True
+            if not progressed:
+                nxt = pending[i].arrival_s - (self.clock() - t0) if i < len(pending) else None
+                wait = self.poll_s if (inflight or nxt is None) else min(max(nxt, 0.0), 0.01)
+                if inflight and nxt is not None:
+                    wait = min(self.poll_s, max(nxt, 0.0))
+                self.sleep(max(wait, 0.0))
+        return Report(done, self.clock() - t0, peak, peak_n, rejected)
+
+
+# ---------------------------------------------------------------------------
+# Executors
+# ---------------------------------------------------------------------------
+
+def request_scanner(req) -> synth.Scanner:
+    """The orbit of a request: the standard 200 degree C-arm orbit sampled with its view count."""
+    return synth.Scanner(n_views=req.n_views)
+
+
+def request_volume(req) -> synth.Volume:
+    return synth.standard_volume(req.L)
+
+
+class FakeExecutor:
+    """Simulated device for scheduler tests: a request takes ``t_fixed + updates / rate`` seconds."""
+
+    def __init__(self, clock, rate_ups: float = 1e12, t_fixed: float = 0.0, bytes_per_pixel=None):
+        self.clock = clock
+        self.rate = rate_ups
+        self.t_fixed = t_fixed
+        self.started = []
+        self.bytes_per_pixel = bytes_per_pixel or {"f32": 4, "f16": 2, "bf16": 2}
+
+    def updates(self, r) -> float:
+        return float(r.L) ** 3 * r.n_views
+
+    def footprint(self, r) -> int:
+        sc = request_scanner(r)
+        return 4 * r.L ** 3 + r.n_views * sc.W * sc.H * self.bytes_per_pixel[r.dtype]
+
+    def start(self, r):
+        self.started.append(r.rid)
+        return (r, self.clock() + self.t_fixed + self.updates(r) / self.rate)
+
+    def poll(self, h) -> bool:
+        return self.clock() >= h[1]
+
+    def finish(self, h):
+        return h[0].rid
+
+
+class GpuExecutor:
+    """Per request: its own stream and context; inputs made on the device at admission, then
+    one back projection of all its views, accumulated into a zeroed volume.
+
+    keep_results: return each volume (on the host) from ``finish``; otherwise a checksum."""
+
+    def __init__(self, device=0, keep_results=False, views_per_pass=0, z_unroll=0, tile_x=0):
+        import torch
+
+        from . import bp
+
+        self.torch = torch
+        self.bp = bp
+        self.dev = torch.device(f"cuda:{device}")
+        self.keep = keep_results
+        self.tuning = (views_per_pass, z_unroll, tile_x)
+        self._mats = {}
+
+    def updates(self, r) -> float:
+        return float(r.L) ** 3 * r.n_views
+
+    def footprint(self, r) -> int:
+        sc = request_scanner(r)
+        bpp = 4 if r.dtype == "f32" else 2
+        vol = 4 * r.L ** 3
+        proj = r.n_views * sc.W * sc.H * bpp
+        k = min(r.n_views, self.tuning[0] or 32)
+        staging = k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
+        cull = (r.L // 16) * (r.L // 16) * (r.L // 4 + 1) * ((r.n_views + 31) // 32) * 4
+        gen = 8 * 3 * 8 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (8 views at a time)
+        return vol + proj + staging + cull + gen
+
+    def _matrices(self, n_views):
+        if n_views not in self._mats:
+            sc = synth.Scanner(n_views=n_views)
+            _, P32 = self.bp.circular_matrices(*sc.geometry_args())
+            self._mats[n_views] = self.torch.from_numpy(P32).to(self.dev)
+        return self._mats[n_views]
+
+    def start(self, r):
+        torch = self.torch
+        stream = torch.cuda.Stream(device=self.dev)  # default priority
+        sc, v = request_scanner(r), request_volume(r)
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[r.dtype]
+        mats = self._matrices(r.n_views)
+        with torch.cuda.stream(stream):
+            proj = synth.filtered_projections(sc, synth.random_ellipsoids(r.phantom_seed), device=self.dev,
+                                              out_dtype=tdt)
+            vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=self.dev)
+        ctx = self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
+        ctx.set_tuning("fused", *self.tuning)
+        ctx.backproject(vol, proj, mats, v.voxel_size, v.origin, stream)
+        done = torch.cuda.Event()
+        done.record(stream)
+        return {"r": r, "stream": stream, "ctx": ctx, "vol": vol, "proj": proj, "done": done}
+
+    def poll(self, h) -> bool:
+        return h["done"].query()
+
+    def finish(self, h):
+        h["done"].synchronize()
+        out = h["vol"].cpu().numpy() if self.keep else float(h["vol"].double().sum())
+        h["ctx"].close()
+        h.clear()
+        return out

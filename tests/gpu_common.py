@@ -16,6 +16,12 @@ TORCH_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat1
 # the compared voxels.
 REL_L2_TOL = 1e-5
 
+# Compact staging rounds the bilinear-patch coefficients (pixel differences) to
+# FP16: unit roundoff u = 2^-11 on each of dx, dy, dxy.  The interpolated value
+# moves by at most u (|dx| + |dy| + |dxy|), which is of the order of u times the
+# local pixel magnitude; the bar on relative L2 is 2u.
+COMPACT_REL_L2_TOL = 2.0 ** -10
+
 
 def rel_l2(got, ref):
     got = np.asarray(got, dtype=np.float64)
@@ -45,7 +51,7 @@ def product_matrices(scanner):
 
 
 def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0, zu=0, init=None,
-            stream=None, tx=0):
+            stream=None, tx=0, wide_staging=None):
     """Back project on cuda:0 through the C ABI; returns the volume as a float32 numpy array."""
     dev = torch.device("cuda:0")
     nz, ny, nx = shape
@@ -54,8 +60,11 @@ def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0,
     p = proj.to(dev).contiguous() if isinstance(proj, torch.Tensor) else torch.from_numpy(proj).to(dev)
     m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
     H, W = p.shape[1:]
+    if wide_staging is None:  # exact FP32 coefficients unless the caller asks for the compact form
+        wide_staging = True
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning(path, k, zu, tx)
+        ctx.set_options(wide_staging=wide_staging)
         ctx.backproject(vol, p, m, voxel_size, origin, stream)
         torch.cuda.synchronize()
     return vol.cpu().numpy()

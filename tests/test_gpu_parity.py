@@ -235,37 +235,41 @@ def strided_sample(L, stride, offset):
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-def test_parity_l512_sampled(dtype):
+@pytest.mark.parametrize("dtype,compact", [("f32", False), ("f16", False), ("bf16", False), ("f16", True),
+                                           ("bf16", True)])
+def test_parity_l512_sampled(dtype, compact):
     """L=512 (voxel 0.5 mm), 496 views, whole volume on the GPU in the default (benchmark)
     configuration.  The bar is relative L2 over the volume: estimated on a uniform sample
     of 64^3 voxels (every 8th per axis), and for three 64^3 blocks as block RMS error over
-    the volume's RMS (a near-empty corner block has a tiny norm of its own)."""
+    the volume's RMS (a near-empty corner block has a tiny norm of its own).  16-bit inputs
+    are compared with the oracle on the same rounded values, with FP32 (wide) staging at
+    the 1e-5 bar and with compact FP16 staging at its derived bar."""
     wl = synth.WORKLOADS["fdk_l512_v496_f32"]
     v = wl.volume
+    tol = gc.COMPACT_REL_L2_TOL if compact else gc.REL_L2_TOL
     proj = gc.full_projections(wl.phantom_seed).to(gc.TORCH_DTYPE[dtype])
     P32 = gc.product_matrices(wl.scanner)
-    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype)
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype, wide_staging=not compact)
     proj_np = proj.float().cpu().numpy()
     xyz = strided_sample(v.L, 8, 3)
     ref_s = oracle.backproject_points(proj_np, P32.astype(np.float64), v.voxel_size, v.origin, xyz)
     got_s = got[xyz[:, 2], xyz[:, 1], xyz[:, 0]]
     err = gc.error_stats(got_s, ref_s)
-    print(f"\nL=512 {dtype} uniform sample: {err}")
-    assert err["rel_l2"] <= gc.REL_L2_TOL, err
+    print(f"\nL=512 {dtype} compact={compact} uniform sample: {err}")
+    assert err["rel_l2"] <= tol, err
     vol_rms = float(np.sqrt(np.mean(ref_s ** 2)))
     for name, blk in L512_BLOCKS.items():
         (x0, x1), (y0, y1), (z0, z1) = blk
         ref = gc.run_oracle(proj_np, P32, v.L, v.voxel_size, v.origin, block=blk)
         d = got[z0:z1, y0:y1, x0:x1].astype(np.float64) - ref
         rel_vol = float(np.sqrt(np.mean(d * d)) / vol_rms)
-        print(f"L=512 {dtype} block {name}: rms error / volume rms = {rel_vol:.3e}, "
+        print(f"L=512 {dtype} compact={compact} block {name}: rms error / volume rms = {rel_vol:.3e}, "
               f"own rel-L2 {gc.rel_l2(got[z0:z1, y0:y1, x0:x1], ref):.3e}")
-        assert rel_vol <= gc.REL_L2_TOL, (name, rel_vol)
+        assert rel_vol <= tol, (name, rel_vol)
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              no_xcd_order=False):
+              xcd_order=False):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -273,7 +277,7 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     n, H, W = p.shape
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
-        ctx.set_options(no_cull=no_cull, no_column=no_column, no_xcd_order=no_xcd_order)
+        ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
@@ -319,8 +323,29 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
     proj32, P32 = small_inputs
     origin = _box_origin(BOX, VS)
     a = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx)
-    b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_xcd_order=True)
+    b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, xcd_order=True)
     c = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_cull=True)
     assert np.array_equal(a, b) and np.array_equal(a, c)
     ref = _oracle_box(proj32, P32, BOX, VS, origin)
     assert gc.rel_l2(a, ref) <= gc.REL_L2_TOL
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("tx,zu", [(16, 8), (64, 1)])
+def test_compact_staging_within_fp16_bound(small_inputs, dtype, tx, zu):
+    """Compact staging (FP16 patch coefficients, per-view power-of-two scale) against the
+    oracle on the same rounded data, within the bar derived from FP16 rounding of the
+    pixel differences; wide staging of the same data meets the FP32 bar."""
+    proj32, P32 = small_inputs
+    proj = proj32.to(gc.TORCH_DTYPE[dtype]) * 1000.0  # large values: the per-view scale must engage
+    origin = _box_origin(BOX, VS)
+    ref = _oracle_box(proj, P32, BOX, VS, origin)
+    compact = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx,
+                         wide_staging=False)
+    wide = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx,
+                      wide_staging=True)
+    e_c, e_w = gc.error_stats(compact, ref), gc.error_stats(wide, ref)
+    print(f"\n{dtype} compact: {e_c}\n{dtype} wide: {e_w}")
+    assert e_w["rel_l2"] <= gc.REL_L2_TOL
+    assert e_c["rel_l2"] <= gc.COMPACT_REL_L2_TOL
+    assert not np.array_equal(compact, wide)

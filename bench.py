@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--zu", type=int, default=0, help="z-unroll (0 = tuned)")
     ap.add_argument("--tx", type=int, default=0, help="block tile width along x (0 = tuned)")
     ap.add_argument("--xcd-order", action="store_true", help="time with the XCD-sliced tile order")
+    ap.add_argument("--xcd-xsplit", action="store_true", help="time with XCD-private x-ranges per z-layer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cull", action="store_true", help="time without the clipping mask")
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
@@ -60,7 +61,7 @@ def log(msg):
 
 
 def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
-              no_column=False, xcd_order=False):
+              no_column=False, xcd_order=False, xcd_xsplit=False):
     path, dt = form.split("_")
     proj = proj_by_dtype[dt]
     n, H, W = proj.shape
@@ -70,7 +71,7 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
     stream = torch.cuda.current_stream(dev)
     ctx = bp.Context(W, H, dt)
     ctx.set_tuning(path, k, zu, tx)
-    ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order)
+    ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order, xcd_xsplit=xcd_xsplit)
     plan = ctx.plan(L, L, L, n)
     for _ in range(warmup):
         ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
@@ -140,7 +141,7 @@ def main():
     results = {}
     for form in forms:
         r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
-                      args.no_cull, args.no_column, args.xcd_order)
+                      args.no_cull, args.no_column, args.xcd_order, args.xcd_xsplit)
         ms = r["step_ms"]
         r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9

@@ -147,6 +147,10 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_NO_COLUMN 2
 #define BP_OPT_XCD_ORDER 4
 #define BP_OPT_WIDE_STAGING 8
+/*   BP_OPT_XCD_XSPLIT  keep the plain z-layer order but give each XCD its own
+ *                     eighth of every layer's x-range (when the tile count along
+ *                     x is a multiple of 8; otherwise plain order) */
+#define BP_OPT_XCD_XSPLIT 16
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */

@@ -166,13 +166,15 @@ class Context:
     OPT_NO_COLUMN = 2
     OPT_XCD_ORDER = 4
     OPT_WIDE_STAGING = 8
+    OPT_XCD_XSPLIT = 16
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, xcd_order: bool = False,
-                    wide_staging: bool = False):
+                    wide_staging: bool = False, xcd_xsplit: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); switch on the
         XCD-sliced tile order or FP32 staging of 16-bit projections (off by default)."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
-                 | (self.OPT_XCD_ORDER if xcd_order else 0) | (self.OPT_WIDE_STAGING if wide_staging else 0))
+                 | (self.OPT_XCD_ORDER if xcd_order else 0) | (self.OPT_WIDE_STAGING if wide_staging else 0)
+                 | (self.OPT_XCD_XSPLIT if xcd_xsplit else 0))
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     KERNELS = {"backproject": 0, "pad": 1, "views": 2}

@@ -297,7 +297,7 @@ bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path
 bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
-    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING))
+    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_XCD_XSPLIT))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     ctx->options = options;
     return BP_OK;
@@ -394,7 +394,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     }
 
     const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
-    const int xcd_order = (ctx->options & BP_OPT_XCD_ORDER) ? 1 : 0;
+    const int xcd_order = (ctx->options & BP_OPT_XCD_ORDER) ? 1 : (ctx->options & BP_OPT_XCD_XSPLIT) ? 2 : 0;
     for (int k0 = 0; k0 < n_views; k0 += plan.k) {
         const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
         const void* src_views = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;

@@ -410,6 +410,8 @@ struct has_column<Patch16Source> {
 // MALL.  With xcd_order, block b takes tile (b % 8) * ceil(T / 8) + b / 8, so
 // each XCD (blocks are dealt to the 8 XCDs round-robin) works through its own
 // contiguous z-range; on MI355X that is slower (8 bands compete for MALL).
+// With xcd_order == 2 the XCDs share the z-layer but each takes its own
+// eighth of the layer's x-range, so its L2 holds a narrower part of the band.
 //
 // cull: optional per-(tile, view) skip bits, `cull_words` words per tile,
 // bit (kbase + k) set when the whole tile projects off the detector in view k
@@ -423,9 +425,17 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
     const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
     const int n_tiles = gx * gy * gz;
     int tile = (int)blockIdx.x;
-    if (xcd_order) {
+    if (xcd_order == 1) {
         const int per = (n_tiles + kXcds - 1) / kXcds;
         tile = (tile % kXcds) * per + tile / kXcds;
+    } else if (xcd_order == 2) {
+        // Shared z-layer, XCD-private x-range: block b runs on XCD b % 8; within the
+        // current z-layer that XCD takes the tiles with bx in its eighth of the layer.
+        // (Launched only when gx is a multiple of 8.)
+        const int xcd = tile % kXcds, j = tile / kXcds;
+        const int gx8 = gx / kXcds, per_layer = gx8 * gy;
+        const int layer = j / per_layer, r = j % per_layer;
+        tile = (layer * gy + r / gx8) * gx + xcd * gx8 + r % gx8;
     }
     if (tile >= n_tiles) return;  // padding blocks of the XCD order (no barriers in this kernel)
     const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
@@ -703,10 +713,11 @@ template <class Src, bool PADDED, int TX>
 hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, int n, const Src& src,
                      const Cull& cl, int xcd_order, hipStream_t s)
 {
+    if (xcd_order == 2 && ((box.nx + TX - 1) / TX) % kXcds != 0) xcd_order = 0;  // x-split needs gx % 8 == 0
     const dim3 block(kBlock, 1, 1);
     auto grid = [&](int z) {
         const long t = n_tiles(box.nx, box.ny, box.nz, z, TX);
-        return dim3((unsigned)(xcd_order ? (t + kXcds - 1) / kXcds * kXcds : t));
+        return dim3((unsigned)(xcd_order == 1 ? (t + kXcds - 1) / kXcds * kXcds : t));
     };
 #define BP_LAUNCH(Z)                                                                                         \
     hipLaunchKernelGGL((backproject_kernel<Src, Z, PADDED, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, \

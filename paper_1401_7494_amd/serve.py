@@ -14,7 +14,6 @@ simulated durations so the scheduling logic is testable on the CPU.
 """
 from __future__ import annotations
 
-import heapq
 import time
 from dataclasses import dataclass, field
 
@@ -179,7 +178,8 @@ class GpuExecutor:
 
     keep_results: return each volume (on the host) from ``finish``; otherwise a checksum."""
 
-    def __init__(self, device=0, keep_results=False, views_per_pass=0, z_unroll=0, tile_x=0):
+    def __init__(self, device=0, keep_results=False, views_per_pass=0, z_unroll=0, tile_x=0,
+                 scanner_fn=request_scanner, volume_fn=request_volume):
         import torch
 
         from . import bp
@@ -189,13 +189,19 @@ class GpuExecutor:
         self.dev = torch.device(f"cuda:{device}")
         self.keep = keep_results
         self.tuning = (views_per_pass, z_unroll, tile_x)
+        self.scanner_fn = scanner_fn
+        self.volume_fn = volume_fn
         self._mats = {}
+        # Free library contexts per (dtype, W, H).  A context's scratch is reused by every
+        # call on it, so one context serves one in-flight request at a time; contexts are
+        # kept for the executor's lifetime (destroying one synchronises the device).
+        self._free_ctx = {}
 
     def updates(self, r) -> float:
         return float(r.L) ** 3 * r.n_views
 
     def footprint(self, r) -> int:
-        sc = request_scanner(r)
+        sc = self.scanner_fn(r)
         bpp = 4 if r.dtype == "f32" else 2
         vol = 4 * r.L ** 3
         proj = r.n_views * sc.W * sc.H * bpp
@@ -205,29 +211,31 @@ class GpuExecutor:
         gen = 8 * 3 * 8 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (8 views at a time)
         return vol + proj + staging + cull + gen
 
-    def _matrices(self, n_views):
-        if n_views not in self._mats:
-            sc = synth.Scanner(n_views=n_views)
+    def _matrices(self, sc):
+        key = sc.geometry_args()[1:] + (sc.n_views, sc.arc_deg, sc.start_deg)
+        if key not in self._mats:
             _, P32 = self.bp.circular_matrices(*sc.geometry_args())
-            self._mats[n_views] = self.torch.from_numpy(P32).to(self.dev)
-        return self._mats[n_views]
+            self._mats[key] = self.torch.from_numpy(P32).to(self.dev)
+        return self._mats[key]
 
     def start(self, r):
         torch = self.torch
         stream = torch.cuda.Stream(device=self.dev)  # default priority
-        sc, v = request_scanner(r), request_volume(r)
+        sc, v = self.scanner_fn(r), self.volume_fn(r)
         tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[r.dtype]
-        mats = self._matrices(r.n_views)
+        mats = self._matrices(sc)
         with torch.cuda.stream(stream):
             proj = synth.filtered_projections(sc, synth.random_ellipsoids(r.phantom_seed), device=self.dev,
                                               out_dtype=tdt)
             vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=self.dev)
-        ctx = self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
+        key = (r.dtype, sc.W, sc.H)
+        pool = self._free_ctx.setdefault(key, [])
+        ctx = pool.pop() if pool else self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
         ctx.set_tuning("fused", *self.tuning)
         ctx.backproject(vol, proj, mats, v.voxel_size, v.origin, stream)
         done = torch.cuda.Event()
         done.record(stream)
-        return {"r": r, "stream": stream, "ctx": ctx, "vol": vol, "proj": proj, "done": done}
+        return {"r": r, "stream": stream, "ctx": ctx, "key": key, "vol": vol, "proj": proj, "done": done}
 
     def poll(self, h) -> bool:
         return h["done"].query()
@@ -235,6 +243,12 @@ class GpuExecutor:
     def finish(self, h):
         h["done"].synchronize()
         out = h["vol"].cpu().numpy() if self.keep else float(h["vol"].double().sum())
-        h["ctx"].close()
+        self._free_ctx[h["key"]].append(h["ctx"])
         h.clear()
         return out
+
+    def close(self):
+        for pool in self._free_ctx.values():
+            for ctx in pool:
+                ctx.close()
+        self._free_ctx.clear()

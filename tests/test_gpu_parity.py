@@ -269,7 +269,7 @@ def test_parity_l512_sampled(dtype, compact):
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              xcd_order=False):
+              xcd_order=False, xcd_xsplit=False):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -277,7 +277,7 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     n, H, W = p.shape
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
-        ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order)
+        ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order, xcd_xsplit=xcd_xsplit)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
@@ -325,7 +325,14 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
     a = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx)
     b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, xcd_order=True)
     c = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_cull=True)
-    assert np.array_equal(a, b) and np.array_equal(a, c)
+    d = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, xcd_xsplit=True)
+    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
+    # a box whose tile count along x is a multiple of 8 takes the x-split order itself
+    shape8 = (9, 20, 8 * tx)
+    o8 = _box_origin(shape8, VS)
+    e = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx)
+    f = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx, xcd_xsplit=True)
+    assert np.array_equal(e, f)
     ref = _oracle_box(proj32, P32, BOX, VS, origin)
     assert gc.rel_l2(a, ref) <= gc.REL_L2_TOL
 
@@ -349,3 +356,18 @@ def test_compact_staging_within_fp16_bound(small_inputs, dtype, tx, zu):
     assert e_w["rel_l2"] <= gc.REL_L2_TOL
     assert e_c["rel_l2"] <= gc.COMPACT_REL_L2_TOL
     assert not np.array_equal(compact, wide)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_stream_checkpoint_resume_is_bit_exact(small_inputs, k):
+    """Views streamed in chunks (the L=1024 mode): stop after a chunk, save the volume on the
+    host, resume into a fresh buffer and context; with the split on a pass boundary the
+    result equals the uninterrupted run bit for bit."""
+    proj32, P32 = small_inputs
+    origin = _box_origin(BOX, VS)
+    whole = gc.run_gpu(proj32, P32, BOX, VS, origin, path="fused", k=k, zu=8)
+    cut = 2 * k if 2 * k < proj32.shape[0] else k
+    ckpt = gc.run_gpu(proj32[:cut], P32[:cut], BOX, VS, origin, path="fused", k=k, zu=8)
+    ckpt = np.array(ckpt, copy=True)  # the checkpoint lives on the host
+    resumed = gc.run_gpu(proj32[cut:], P32[cut:], BOX, VS, origin, path="fused", k=k, zu=8, init=ckpt)
+    assert np.array_equal(resumed, whole)

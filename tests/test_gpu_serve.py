@@ -1,0 +1,32 @@
+"""Serving on the GPU: each request's volume is the same alone and in a concurrent mix."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1401_7494_amd import serve, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def small_scanner(r):
+    return synth.Scanner(n_views=r.n_views, W=160, H=120, pitch=2.5)
+
+
+def small_volume(r):
+    return synth.Volume(r.L, 192.0 / r.L)
+
+
+def test_results_are_the_same_alone_and_in_the_mix():
+    rng = np.random.default_rng(1405)
+    reqs = [synth.Request(i, 0.002 * i, int(rng.choice([32, 48, 64])), int(rng.choice([12, 24, 36])),
+                          str(rng.choice(["f32", "f16"])), 100000 + i) for i in range(8)]
+    kw = dict(keep_results=True, scanner_fn=small_scanner, volume_fn=small_volume)
+    mix = serve.Server(serve.GpuExecutor(**kw), budget_bytes=8 * serve.GIB, max_inflight=4).run(reqs)
+    assert len(mix.completed) == 8 and mix.peak_inflight > 1
+    alone = {}
+    for r in reqs:
+        rep = serve.Server(serve.GpuExecutor(**kw), budget_bytes=8 * serve.GIB, max_inflight=1).run([r])
+        alone[r.rid] = rep.completed[0].result
+    for c in mix.completed:
+        assert np.array_equal(c.result, alone[c.rid]), f"request {c.rid} differs in the mix"
+        assert np.abs(c.result).max() > 0

@@ -30,9 +30,40 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_PER_UPDATE = 22  # minimal VALU instructions per voxel update of the fused form
+# Minimal VALU instructions per voxel update of the fused pass on a column view
+# (row FMA, clamp, convert, fraction, index mad, three patch FMAs, accumulate),
+# counted in the gfx950 ISA of backproject_kernel.
+VALU_PER_UPDATE = 9
 VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes/clk x 2.4 GHz, lane-instructions/s (no packed FP32)
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1401_7494_amd/csrc/bp_kernels.hip", "paper_1401_7494_amd/csrc/bp_internal.h")
+COUNTERS_MD = "profiles/backproject_fused_f32_l512_v496_counters.md"
+
+
+def kernel_source_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the fused FP32 pass from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when the kernel sources
+    have changed since the counters were taken."""
+    path = os.path.join(ROOT, COUNTERS_MD)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if rec.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"]) * 1024
 
 
 def parse():
@@ -45,8 +76,8 @@ def parse():
     ap.add_argument("--k", type=int, default=0, help="views per pass for fused forms (0 = tuned)")
     ap.add_argument("--zu", type=int, default=0, help="z-unroll (0 = tuned)")
     ap.add_argument("--tx", type=int, default=0, help="block tile width along x (0 = tuned)")
-    ap.add_argument("--xcd-order", action="store_true", help="time with the XCD-sliced tile order")
-    ap.add_argument("--xcd-xsplit", action="store_true", help="time with XCD-private x-ranges per z-layer")
+    ap.add_argument("--order", default="region", choices=("region", "plain", "zslices"), help="tile order")
+    ap.add_argument("--region-ax", type=int, default=0, help="XCD regions along x for --order region (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cull", action="store_true", help="time without the clipping mask")
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
@@ -61,7 +92,7 @@ def log(msg):
 
 
 def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
-              no_column=False, xcd_order=False, xcd_xsplit=False):
+              no_column=False, order="region", region_ax=0):
     path, dt = form.split("_")
     proj = proj_by_dtype[dt]
     n, H, W = proj.shape
@@ -71,7 +102,7 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
     stream = torch.cuda.current_stream(dev)
     ctx = bp.Context(W, H, dt)
     ctx.set_tuning(path, k, zu, tx)
-    ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order, xcd_xsplit=xcd_xsplit)
+    ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax)
     plan = ctx.plan(L, L, L, n)
     for _ in range(warmup):
         ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
@@ -141,7 +172,7 @@ def main():
     results = {}
     for form in forms:
         r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
-                      args.no_cull, args.no_column, args.xcd_order, args.xcd_xsplit)
+                      args.no_cull, args.no_column, args.order, args.region_ax)
         ms = r["step_ms"]
         r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9
@@ -183,8 +214,10 @@ def main():
     per_launch_ms = ms_bp / max(n_bp, 1)
     updates_per_launch = updates * args.steps / max(n_bp, 1)
     achieved = updates_per_launch * VALU_PER_UPDATE / (per_launch_ms * 1e-3) / 1e12
+    traffic = measured_traffic() if head is results.get("fused_f32") else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_T, 3),
-                "unit": "Tinstr/s", "frac": round(achieved / VALU_PEAK_T, 4), "traffic": None,
+                "unit": "Tinstr/s", "frac": round(achieved / VALU_PEAK_T, 4),
+                "traffic": round(traffic) if traffic else None,
                 "kernel": "backproject_kernel", "avg_launch_ms": round(per_launch_ms, 4),
                 "updates_per_launch": updates_per_launch, "valu_instr_per_update": VALU_PER_UPDATE}
 

@@ -139,18 +139,23 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     compact FP16 coefficients (8 bytes, scaled per view by a
  *                     power of two; adds the rounding of the pixel differences
  *                     to FP16, ~2^-11 relative)
- *   BP_OPT_XCD_ORDER  deal contiguous z-ranges of tiles to the 8 XCDs instead of
- *                     the default plain tile order (x fastest; measured faster on
- *                     MI355X, where all XCDs then share one detector-row band in MALL)
+ *
+ *   Tile order (which blocks run together; results are identical in every order):
+ *   default           XCD-private regions: all XCDs work through the same z-layer of
+ *                     tiles, each on its own ax x (8/ax) region of it (ax = 8 unless set
+ *                     below; plain order if the tile grid does not divide)
+ *   BP_OPT_XCD_REGION(ax)  choose ax in {1, 2, 4, 8}
+ *   BP_OPT_PLAIN_ORDER     tiles in plain order, x fastest
+ *   BP_OPT_XCD_ORDER  deal contiguous z-ranges of tiles to the 8 XCDs (measured slowest)
  */
 #define BP_OPT_NO_CULL 1
 #define BP_OPT_NO_COLUMN 2
 #define BP_OPT_XCD_ORDER 4
 #define BP_OPT_WIDE_STAGING 8
-/*   BP_OPT_XCD_XSPLIT  keep the plain z-layer order but give each XCD its own
- *                     eighth of every layer's x-range (when the tile count along
- *                     x is a multiple of 8; otherwise plain order) */
-#define BP_OPT_XCD_XSPLIT 16
+#define BP_OPT_PLAIN_ORDER 16
+#define BP_OPT_XCD_REGION_SHIFT 5
+#define BP_OPT_XCD_REGION_MASK (15 << BP_OPT_XCD_REGION_SHIFT)
+#define BP_OPT_XCD_REGION(ax) ((ax) << BP_OPT_XCD_REGION_SHIFT)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */

@@ -166,15 +166,24 @@ class Context:
     OPT_NO_COLUMN = 2
     OPT_XCD_ORDER = 4
     OPT_WIDE_STAGING = 8
-    OPT_XCD_XSPLIT = 16
+    OPT_PLAIN_ORDER = 16
+    OPT_XCD_REGION_SHIFT = 5
+    ORDERS = ("region", "plain", "zslices")
 
-    def set_options(self, no_cull: bool = False, no_column: bool = False, xcd_order: bool = False,
-                    wide_staging: bool = False, xcd_xsplit: bool = False):
-        """Switch off the clipping mask or the column specialisation (on by default); switch on the
-        XCD-sliced tile order or FP32 staging of 16-bit projections (off by default)."""
+    def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
+                    order: str = "region", region_ax: int = 0):
+        """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
+        projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
+        each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices")."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
-                 | (self.OPT_XCD_ORDER if xcd_order else 0) | (self.OPT_WIDE_STAGING if wide_staging else 0)
-                 | (self.OPT_XCD_XSPLIT if xcd_xsplit else 0))
+                 | (self.OPT_WIDE_STAGING if wide_staging else 0))
+        if order == "plain":
+            flags |= self.OPT_PLAIN_ORDER
+        elif order == "zslices":
+            flags |= self.OPT_XCD_ORDER
+        elif order != "region":
+            raise ValueError(f"order must be one of {self.ORDERS}")
+        flags |= int(region_ax) << self.OPT_XCD_REGION_SHIFT
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     KERNELS = {"backproject": 0, "pad": 1, "views": 2}

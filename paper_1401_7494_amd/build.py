@@ -17,6 +17,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbp.so")
 SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_geometry.cpp"]
+# The seeded input generator's GPU kernels: a library of their own, not linked into libbp.so.
+SYNTH_LIB = os.path.join(HERE, "libbpsynth.so")
+SYNTH_SOURCES = ["synth_kernels.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU ops are disabled for all device code.
@@ -32,10 +35,15 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    _build_lib(SYNTH_SOURCES, SYNTH_LIB, verbose)
+    return _build_lib(SOURCES, LIB, verbose)
+
+
+def _build_lib(sources, lib_path, verbose):
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src in SOURCES:
+    for src in sources:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc(), f"--offload-arch={ARCH}", *COMMON, *DEVICE_FLAGS,
@@ -48,13 +56,13 @@ def build(verbose: bool = False) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"linking libbp.so failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"linking {os.path.basename(lib_path)} failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

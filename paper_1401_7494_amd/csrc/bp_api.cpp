@@ -49,6 +49,8 @@ struct bp_ctx_s {
 namespace {
 
 const char* const kVersion = "0.1.0";
+// XCD-private region split of each z-layer: ax regions along x, 8 / ax along y (measured at L = 512).
+const int kDefaultRegionAx = 8;
 
 bp_status fail(bp_ctx ctx, bp_status st, const std::string& msg)
 {
@@ -297,8 +299,12 @@ bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path
 bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
-    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_XCD_XSPLIT))
+    if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
+                    BP_OPT_XCD_REGION_MASK))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
+    const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
+    if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
+        return fail(ctx, BP_ERR_INVALID_ARG, "XCD region split must be 1, 2, 4 or 8 along x");
     ctx->options = options;
     return BP_OK;
 }
@@ -394,7 +400,11 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     }
 
     const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
-    const int xcd_order = (ctx->options & BP_OPT_XCD_ORDER) ? 1 : (ctx->options & BP_OPT_XCD_XSPLIT) ? 2 : 0;
+    // tile order: XCD z-slices (opt-in), plain (opt-in), else XCD-private regions of each z-layer
+    int xcd_order = 2 * kDefaultRegionAx;
+    if (const int r = (ctx->options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT) xcd_order = 2 * r;
+    if (ctx->options & BP_OPT_PLAIN_ORDER) xcd_order = 0;
+    if (ctx->options & BP_OPT_XCD_ORDER) xcd_order = 1;
     for (int k0 = 0; k0 < n_views; k0 += plan.k) {
         const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
         const void* src_views = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;

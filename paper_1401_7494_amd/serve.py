@@ -179,7 +179,7 @@ class GpuExecutor:
     keep_results: return each volume (on the host) from ``finish``; otherwise a checksum."""
 
     def __init__(self, device=0, keep_results=False, views_per_pass=0, z_unroll=0, tile_x=0,
-                 scanner_fn=request_scanner, volume_fn=request_volume):
+                 scanner_fn=request_scanner, volume_fn=request_volume, fast_inputs=True):
         import torch
 
         from . import bp
@@ -191,6 +191,7 @@ class GpuExecutor:
         self.tuning = (views_per_pass, z_unroll, tile_x)
         self.scanner_fn = scanner_fn
         self.volume_fn = volume_fn
+        self.fast_inputs = fast_inputs
         self._mats = {}
         # Free library contexts per (dtype, W, H).  A context's scratch is reused by every
         # call on it, so one context serves one in-flight request at a time; contexts are
@@ -208,7 +209,7 @@ class GpuExecutor:
         k = min(r.n_views, self.tuning[0] or 32)
         staging = k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
         cull = (r.L // 16) * (r.L // 16) * (r.L // 4 + 1) * ((r.n_views + 31) // 32) * 4
-        gen = 8 * 3 * 8 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (8 views at a time)
+        gen = 6 * 62 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (62 views at a time)
         return vol + proj + staging + cull + gen
 
     def _matrices(self, sc):
@@ -226,7 +227,7 @@ class GpuExecutor:
         mats = self._matrices(sc)
         with torch.cuda.stream(stream):
             proj = synth.filtered_projections(sc, synth.random_ellipsoids(r.phantom_seed), device=self.dev,
-                                              out_dtype=tdt)
+                                              out_dtype=tdt, chunk=62, fast=self.fast_inputs)
             vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=self.dev)
         key = (r.dtype, sc.W, sc.H)
         pool = self._free_ctx.setdefault(key, [])

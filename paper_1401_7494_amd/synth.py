@@ -122,6 +122,51 @@ def _detector_offsets(scanner: Scanner, device):
     return i * scanner.pitch, j * scanner.pitch  # mm along e_u, e_v
 
 
+_SYNTH_LIB = None
+
+
+def _synth_lib():
+    """The generator's GPU kernels (libbpsynth.so), or None if not built."""
+    global _SYNTH_LIB
+    if _SYNTH_LIB is None:
+        import ctypes
+        import os
+
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbpsynth.so")
+        if not os.path.exists(path):
+            return None
+        lib = ctypes.CDLL(path)
+        lib.bpsynth_line_integrals.restype = ctypes.c_int
+        lib.bpsynth_line_integrals.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_void_p]
+        _SYNTH_LIB = lib
+    return _SYNTH_LIB
+
+
+def line_integrals_fast(scanner: Scanner, phantom: Ellipsoids, views, device) -> torch.Tensor:
+    """Same as ``line_integrals`` by one GPU kernel per call (libbpsynth.so) on torch's current stream."""
+    lib = _synth_lib()
+    if lib is None:
+        raise RuntimeError("libbpsynth.so is not built")
+    views = list(views)
+    src, det, e_u, e_v = _frames(scanner, views, device)
+    frames = torch.cat([src, det, e_u, e_v], dim=1).contiguous()
+    ell = []
+    for e in range(len(phantom.densities)):
+        R = phantom.rotations[e]
+        M = R @ np.diag(1.0 / phantom.axes[e] ** 2) @ R.T
+        ell.append(np.concatenate([phantom.centres[e], M.ravel(), [phantom.densities[e]]]))
+    ell = torch.as_tensor(np.array(ell, dtype=np.float64).reshape(-1, 13), device=device).contiguous()
+    out = torch.empty((len(views), scanner.H, scanner.W), dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(out.device).cuda_stream
+    rc = lib.bpsynth_line_integrals(out.data_ptr(), frames.data_ptr(), len(views), scanner.W, scanner.H,
+                                    float(scanner.pitch), ell.data_ptr(), len(phantom.densities), stream)
+    if rc != 0:
+        raise RuntimeError(f"bpsynth_line_integrals failed ({rc})")
+    return out
+
+
 def line_integrals(scanner: Scanner, phantom: Ellipsoids, views, device="cpu") -> torch.Tensor:
     """Analytic line integrals (V, H, W) FP64 of the phantom along source -> pixel-centre rays.
 
@@ -189,18 +234,21 @@ def fdk_filter(p: torch.Tensor, scanner: Scanner) -> torch.Tensor:
 
 def filtered_projections(scanner: Scanner, phantom: Ellipsoids, device="cpu", views=None,
                          chunk: int = 8, out_dtype=torch.float32, noise_frac: float = 0.0,
-                         noise_seed: int = 0) -> torch.Tensor:
+                         noise_seed: int = 0, fast: bool = False) -> torch.Tensor:
     """Filtered, weighted projections (V, H, W) as ``out_dtype`` (FP32/FP16/BF16, round-to-nearest-even).
 
     noise_frac > 0 adds Gaussian noise of sigma = noise_frac * max|p| over the
     whole stack to the filtered FP64 pixels before rounding (separate seed).
+    fast: compute the line integrals with the generator's GPU kernel (device
+    must be a GPU; equal to the torch path up to FP64 rounding order).
     """
     views = list(range(scanner.n_views)) if views is None else list(views)
+    integrals = line_integrals_fast if fast else line_integrals
     out64 = [] if noise_frac > 0 else None
     out = torch.empty((len(views), scanner.H, scanner.W), dtype=out_dtype, device=device)
     for a in range(0, len(views), chunk):
         vs = views[a:a + chunk]
-        f = fdk_filter(line_integrals(scanner, phantom, vs, device), scanner)
+        f = fdk_filter(integrals(scanner, phantom, vs, device), scanner)
         if out64 is not None:
             out64.append(f.to(torch.float32))  # keeps memory bounded; noise is added below
         else:

@@ -178,7 +178,8 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_set_tuning(h, 9, 0, 0, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 3, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_options(h, 64) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 1 << 12) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 3 << 5) == bp.BP_ERR_INVALID_ARG  # region split of 3 along x
         torch.cuda.synchronize()
     assert not vol.any()
 
@@ -269,7 +270,7 @@ def test_parity_l512_sampled(dtype, compact):
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              xcd_order=False, xcd_xsplit=False):
+              order="region", region_ax=0):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -277,7 +278,7 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     n, H, W = p.shape
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
-        ctx.set_options(no_cull=no_cull, no_column=no_column, xcd_order=xcd_order, xcd_xsplit=xcd_xsplit)
+        ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
@@ -318,21 +319,23 @@ def test_column_branch_needs_exact_zeros():
 @pytest.mark.parametrize("tx", [8, 16, 32, 64])
 @pytest.mark.parametrize("zu", [1, 4, 8])
 def test_tile_shapes_and_block_order(small_inputs, tx, zu):
-    """Every block tile shape covers the ragged box exactly once; the XCD tile order
-    changes no bit; culling stays exact for every shape."""
+    """Every block tile shape covers the ragged box exactly once; every tile order changes
+    no bit; culling stays exact for every shape."""
     proj32, P32 = small_inputs
     origin = _box_origin(BOX, VS)
-    a = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx)
-    b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, xcd_order=True)
+    a = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, order="plain")
+    for order, ax in (("zslices", 0), ("region", 0), ("region", 1), ("region", 2), ("region", 4)):
+        b = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, order=order, region_ax=ax)
+        assert np.array_equal(a, b), (order, ax)
     c = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_cull=True)
-    d = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, xcd_xsplit=True)
-    assert np.array_equal(a, b) and np.array_equal(a, c) and np.array_equal(a, d)
-    # a box whose tile count along x is a multiple of 8 takes the x-split order itself
-    shape8 = (9, 20, 8 * tx)
+    assert np.array_equal(a, c)
+    # a box whose tile grid divides into XCD regions takes the region order itself
+    shape8 = (9, 8 * (256 // tx), 8 * tx)
     o8 = _box_origin(shape8, VS)
-    e = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx)
-    f = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx, xcd_xsplit=True)
-    assert np.array_equal(e, f)
+    e = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx, order="plain")
+    for ax in (1, 2, 4, 8):
+        f = _run_opts(proj32, P32, shape8, VS, o8, k=5, zu=zu, tx=tx, order="region", region_ax=ax)
+        assert np.array_equal(e, f), ax
     ref = _oracle_box(proj32, P32, BOX, VS, origin)
     assert gc.rel_l2(a, ref) <= gc.REL_L2_TOL
 

@@ -30,3 +30,18 @@ def test_results_are_the_same_alone_and_in_the_mix():
     for c in mix.completed:
         assert np.array_equal(c.result, alone[c.rid]), f"request {c.rid} differs in the mix"
         assert np.abs(c.result).max() > 0
+
+
+def test_fast_generator_matches_the_torch_generator():
+    """The generator's GPU line-integral kernel equals the torch formulation (FP64 rounding only)."""
+    sc = synth.Scanner(n_views=5, W=200, H=150, pitch=1.5)
+    ph = synth.random_ellipsoids(100003)
+    dev = torch.device("cuda:0")
+    a = synth.line_integrals(sc, ph, range(5), device=dev)
+    b = synth.line_integrals_fast(sc, ph, range(5), device=dev)
+    torch.cuda.synchronize()
+    assert float(a.abs().max()) > 10.0
+    assert float((a - b).abs().max()) <= 1e-9 * float(a.abs().max())
+    fa = synth.filtered_projections(sc, ph, device=dev)
+    fb = synth.filtered_projections(sc, ph, device=dev, fast=True)
+    assert float((fa - fb).abs().max()) <= 1e-6 * float(fa.abs().max())

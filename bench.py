@@ -148,7 +148,8 @@ def main():
     dev = torch.device("cuda:0")
     log(f"bench: workload {wl.name} L={v.L} views={sc.n_views} det={sc.W}x{sc.H} on {torch.cuda.get_device_name(0)}")
     t = time.perf_counter()
-    proj32 = synth.filtered_projections(sc, synth.random_ellipsoids(wl.phantom_seed), device=dev)
+    proj32 = synth.filtered_projections(sc, synth.random_ellipsoids(wl.phantom_seed), device=dev,
+                                        noise_frac=wl.noise_frac, noise_seed=wl.noise_seed)
     torch.cuda.synchronize()
     log(f"bench: inputs generated on the GPU in {time.perf_counter() - t:.1f} s")
     if args.copy_calibration:
@@ -248,6 +249,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded random-ellipsoid phantom standing in for the RabbitCT dataset)",
         "config": {"workload": wl.name, "L": v.L, "voxel_mm": v.voxel_size, "views": sc.n_views,
+                   "noise_frac": wl.noise_frac,
                    "detector": [sc.W, sc.H], "form": "fused_f32", "parallelism": "single GPU"},
         "p50_gups": round(head["gups_p50"], 2),
         "p99_gups": round(head["gups_p99"], 2),

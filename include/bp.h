@@ -83,7 +83,8 @@ typedef struct {
     int views_per_pass;   /* K for BP_PATH_FUSED; 0 = tuned */
     int z_unroll;         /* voxels per thread along z (1, 2, 4 or 8); 0 = tuned */
     int tile_x;           /* columns along x per 256-thread block (8, 16, 32 or 64; the block is
-                             tile_x x 256/tile_x columns); 0 = tuned.  BP_PATH_PLAIN uses 64. */
+                             tile_x x 256/tile_x columns); 0 = tuned.  BP_PATH_PLAIN takes 16
+                             or 64 (others give 64). */
 } bp_config;
 
 /* Fill *cfg with defaults: device 0, 1248 x 960, FP32, AUTO, tuned K, z_unroll and tile_x. */

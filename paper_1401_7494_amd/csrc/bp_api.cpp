@@ -42,8 +42,7 @@ struct bp_ctx_s {
     double total_ms[3] = {0, 0, 0};
     long long launches[3] = {0, 0, 0};
     std::vector<hipEvent_t> event_pool;
-    // staging layout of the fused path (BP_FUSED_LAYOUT=pairs|patch, read at bp_create)
-    bp::Layout fused_layout = bp::Layout::Patch;
+
 };
 
 namespace {
@@ -170,8 +169,9 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     while (p.zu > 1 && p.zu > nz) p.zu >>= 1;
     p.tx = ctx->tx_override > 0 ? ctx->tx_override : ctx->cfg.tile_x;
     if (p.tx <= 0) p.tx = 16;
-    // the plain path and the pair layout come in 64-wide tiles only
-    if (p.path == BP_PATH_PLAIN || ctx->fused_layout != bp::Layout::Patch) p.tx = 64;
+    // the plain path comes in 16- and 64-wide tiles, the pair layout in 64-wide tiles
+    if (p.path == BP_PATH_PLAIN && p.tx != 16) p.tx = 64;
+
     (void)nx;
     (void)ny;
     return p;
@@ -241,9 +241,6 @@ bp_status bp_create(const bp_config* cfg, bp_ctx* out)
     bp_ctx ctx = new (std::nothrow) bp_ctx_s();
     if (!ctx) return BP_ERR_OUT_OF_MEMORY;
     ctx->cfg = *cfg;
-    if (const char* l = std::getenv("BP_FUSED_LAYOUT")) {
-        if (std::strcmp(l, "pairs") == 0) ctx->fused_layout = bp::Layout::Pairs;
-    }
     *out = ctx;
     return BP_OK;
 }
@@ -366,7 +363,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                           sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
     if (st != BP_OK) return st;
     if (ctx->views_cap < sizeof(bp::ViewConst) * (size_t)n_views) return BP_ERR_OUT_OF_MEMORY;
-    bp::Layout layout = plan.path == BP_PATH_FUSED ? ctx->fused_layout : bp::Layout::Checked;
+    bp::Layout layout = plan.path == BP_PATH_FUSED ? bp::Layout::Patch : bp::Layout::Checked;
     if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
         layout = bp::Layout::Patch16;
     if (layout != bp::Layout::Checked) {
@@ -414,12 +411,9 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             uint32_t* maxabs = (uint32_t*)ctx->d_scale;
             float* inv_scale = ctx->d_scale ? (float*)ctx->d_scale + plan.k : nullptr;
             e = timed(ctx, 1, s, [&] {
-                switch (layout) {
-                case bp::Layout::Patch: return bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s);
-                case bp::Layout::Patch16:
-                    return bp::launch_patch16(dt, src_views, W, H, kc, ctx->d_pad, maxabs, inv_scale, s);
-                default: return bp::launch_pad(dt, src_views, W, H, kc, ctx->d_pad, s);
-                }
+                return layout == bp::Layout::Patch16
+                           ? bp::launch_patch16(dt, src_views, W, H, kc, ctx->d_pad, maxabs, inv_scale, s)
+                           : bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s);
             });
             if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
             e = timed(ctx, 0, s, [&] {

@@ -34,7 +34,6 @@ enum class Dtype : int { F32 = 0, F16 = 1, BF16 = 2 };
 // Where a back-projection pass reads its taps from.
 enum class Layout : int {
     Checked = 0,  // the caller's images, per-tap detector bounds (plain path)
-    Pairs = 1,    // zero-padded staging copy, 4-byte elements (FP32 pixel or 16-bit pair)
     Patch = 2,    // bilinear-patch staging copy, 16-byte FP32 coefficients per element
     Patch16 = 3   // bilinear-patch staging copy, 8-byte scaled FP16 coefficients per element
 };
@@ -50,19 +49,12 @@ inline size_t staged_view_bytes(Layout l, int W, int H)
 {
     if (l == Layout::Patch) return (size_t)(W + 2) * (size_t)(H + 2) * 16u;
     if (l == Layout::Patch16) return (size_t)(W + 2) * (size_t)(H + 2) * 8u;
-    if (l == Layout::Pairs) return (size_t)(W + 3) * (size_t)(H + 3) * 4u;
     return 0;
 }
 
 // column_ok = false keeps every safe view on the general (per-voxel) branch.
 hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, bool column_ok, ViewConst* out,
                              hipStream_t s);
-
-// Copy views [0, n) of `proj` (dtype dt, H x W each) into the zero-padded
-// staging layout: FP32 -> float per element; FP16/BF16 -> packed pairs
-// (pixel i, pixel i+1) per element.
-hipError_t launch_pad(Dtype dt, const void* proj, int W, int H, int n, void* padded,
-                      hipStream_t s);
 
 // Bilinear-patch staging copy of views [0, n) of `proj`.
 hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, hipStream_t s);
@@ -74,8 +66,8 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 
 // One volume pass over views [0, n) of the given view constants; `src` is the
 // caller's images (Layout::Checked) or the staging copy of that layout.
-// tile_x: columns along x per block (64, 32, 16 or 8; the plain path and
-// the pair layout take 64 only); a block covers tile_x x (256 / tile_x)
+// tile_x: columns along x per block (64, 32, 16 or 8; the plain path takes
+// 16 or 64); a block covers tile_x x (256 / tile_x)
 // columns.  xcd_order: deal contiguous z-ranges of tiles to the 8 XCDs.
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,

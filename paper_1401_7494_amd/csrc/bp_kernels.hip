@@ -15,11 +15,12 @@
 //   * Part 1 hoists the (x, y) terms out of the z loop: u, v, w cost one FMA
 //     each per voxel; 1/w is the hardware reciprocal (Sec. 5.1 makes the same
 //     substitution on the CPUs).
-//   * Part 2 uses buffer loads: 32-bit offsets, and hardware range checks
-//     that return 0 past the end of a view instead of faulting.  With the
-//     zero-padded staging copy (Sec. 5.1.1) the tap position is clamped into
-//     the padded frame and the four taps need no tests; horizontally adjacent
-//     taps are fetched together (the pairwise loads of Sec. 6.1).
+//   * Part 2 uses buffer loads with 32-bit offsets.  The fused pass reads a
+//     staging copy of the views in which every pixel carries the four
+//     coefficients of its bilinear patch and the detector has a one-pixel zero
+//     border (the zero-padded copy of Sec. 5.1.1): the position is clamped
+//     into the bordered frame, so the taps need no tests, and one aligned
+//     16-byte (8-byte for 16-bit data) load replaces the four taps.
 //   * A view whose matrix puts some voxel of the box behind (or too near) the
 //     source plane takes a guarded branch that zeroes such contributions; the
 //     branch is uniform per view, decided once per call.
@@ -50,20 +51,15 @@ __device__ __forceinline__ float f16_lo(uint32_t v)
 {
     return __half2float(__builtin_bit_cast(__half, (unsigned short)(v & 0xffffu)));
 }
-__device__ __forceinline__ float f16_hi(uint32_t v)
-{
-    return __half2float(__builtin_bit_cast(__half, (unsigned short)(v >> 16)));
-}
 __device__ __forceinline__ float bf16_lo(uint32_t v) { return u32_as_f32(v << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t v) { return u32_as_f32(v & 0xffff0000u); }
 
 // ---------------------------------------------------------------------------
 // Tap sources.  Each provides, for one view, the four taps around a position.
 // ---------------------------------------------------------------------------
 
 // Plain path: the caller's W x H image of T.  Positions are raw detector
-// coordinates; a tap off the detector reads 0 (column test in VALU, row test
-// by the buffer range check: rows -1 and H fall outside the view's bytes).
+// coordinates; a tap off the detector reads 0 (row and column tests in VALU;
+// every load stays inside the view).
 template <typename T>
 struct CheckedSource {
     static constexpr uint32_t kElem = sizeof(T);
@@ -82,7 +78,7 @@ struct CheckedSource {
 
     __device__ __forceinline__ float tap(const View& v, int idx) const
     {
-        const uint32_t off = (uint32_t)idx * kElem;  // negative idx wraps past the end -> 0
+        const uint32_t off = (uint32_t)idx * kElem;
         if constexpr (sizeof(T) == 4) {
             return u32_as_f32(__builtin_amdgcn_raw_buffer_load_b32(v.rs, off, 0, 0));
         } else {
@@ -92,8 +88,20 @@ struct CheckedSource {
         }
     }
 
+    // Taps (i0, j) and (i0+1, j) of row j, 0 off the detector.  Indices are
+    // clamped into the image before loading, so every load is in bounds.
+    __device__ __forceinline__ void taps_row(const View& v, int i0, int j, float& a, float& b) const
+    {
+        const bool c0 = i0 >= 0, c1 = i0 + 1 < W, rj = (j >= 0) & (j < H);
+        const int row = min(max(j, 0), H - 1) * W;
+        const float ta = tap(v, row + max(i0, 0));
+        const float tb = tap(v, row + min(i0 + 1, W - 1));
+        a = (rj & c0) ? ta : 0.0f;
+        b = (rj & c1) ? tb : 0.0f;
+    }
+
     // Contribution of one view at (u, v, w); 0 unless w > 0 and the position
-    // lies strictly inside (-1, W) x (-1, H).
+    // lies strictly inside (-1, W) x (-1, H), each tap 0 off the detector.
     __device__ __forceinline__ float contrib(const View& vw, float u, float v, float w) const
     {
         const float r = __builtin_amdgcn_rcpf(w);
@@ -104,97 +112,9 @@ struct CheckedSource {
         const float fs = floorf(s), ft = floorf(t);
         const int i0 = (int)fs, j0 = (int)ft;
         const float fx = s - fs, fy = t - ft;
-        const bool c0 = i0 >= 0, c1 = i0 + 1 < W;
-        const int idx = j0 * W + i0;
-        const float a = c0 ? tap(vw, idx) : 0.0f;
-        const float b = c1 ? tap(vw, idx + 1) : 0.0f;
-        const float c = c0 ? tap(vw, idx + W) : 0.0f;
-        const float d = c1 ? tap(vw, idx + W + 1) : 0.0f;
-        const float top = fmaf(fx, b - a, a);
-        const float bot = fmaf(fx, d - c, c);
-        const float val = fmaf(fy, bot - top, top);
-        return ok ? val * (r * r) : 0.0f;
-    }
-};
-
-// Fused path: zero-padded staging copy, (W + 3) x (H + 3) elements of 4 bytes;
-// pixel (i, j) sits at element (j + 1) * pitch + (i + 1).  Element types:
-//   Dtype::F32  -> one float per element; a dword pair load fetches two columns.
-//   Dtype::F16/BF16 -> a packed pair (pixel i, pixel i+1) per element.
-template <Dtype DT>
-struct PaddedSource {
-    const uint8_t* base;
-    int W, H;
-
-    struct View {
-        __amdgpu_buffer_rsrc_t rs;
-    };
-
-    __device__ __forceinline__ int pitch() const { return W + 3; }
-
-    __device__ __forceinline__ View view(int k) const
-    {
-        const uint32_t bytes = (uint32_t)(W + 3) * (uint32_t)(H + 3) * 4u;
-        return View{make_rsrc(base + (size_t)k * bytes, bytes)};
-    }
-
-    __device__ __forceinline__ void taps(const View& vw, int i0, int j0, float& a, float& b,
-                                         float& c, float& d) const
-    {
-        const uint32_t pitch_b = (uint32_t)pitch() * 4u;
-        const uint32_t off = (__umul24((uint32_t)j0, (uint32_t)pitch()) + (uint32_t)i0) * 4u;
-        if constexpr (DT == Dtype::F32) {
-            const auto r0 = __builtin_amdgcn_raw_buffer_load_b64(vw.rs, off, 0, 0);
-            const auto r1 = __builtin_amdgcn_raw_buffer_load_b64(vw.rs, off, pitch_b, 0);
-            a = u32_as_f32(r0[0]);
-            b = u32_as_f32(r0[1]);
-            c = u32_as_f32(r1[0]);
-            d = u32_as_f32(r1[1]);
-        } else {
-            const uint32_t p0 = __builtin_amdgcn_raw_buffer_load_b32(vw.rs, off, 0, 0);
-            const uint32_t p1 = __builtin_amdgcn_raw_buffer_load_b32(vw.rs, off, pitch_b, 0);
-            if constexpr (DT == Dtype::F16) {
-                a = f16_lo(p0); b = f16_hi(p0); c = f16_lo(p1); d = f16_hi(p1);
-            } else {
-                a = bf16_lo(p0); b = bf16_hi(p0); c = bf16_lo(p1); d = bf16_hi(p1);
-            }
-        }
-    }
-
-    // Every voxel of the box has w >= 1e-4 * max w > 0: clamp the padded
-    // position into [0, W+1] x [0, H+1]; clamped positions see only pad zeros
-    // (or carry zero weight), exactly as the unbounded image would.
-    __device__ __forceinline__ float contrib_safe(const View& vw, float u, float v, float w) const
-    {
-        const float r = __builtin_amdgcn_rcpf(w);
-        const float s = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
-        const float t = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
-        const int i0 = (int)s, j0 = (int)t;  // s, t >= 0: truncation is floor
-        const float fx = __builtin_amdgcn_fractf(s);
-        const float fy = __builtin_amdgcn_fractf(t);
         float a, b, c, d;
-        taps(vw, i0, j0, a, b, c, d);
-        const float top = fmaf(fx, b - a, a);
-        const float bot = fmaf(fx, d - c, c);
-        const float val = fmaf(fy, bot - top, top);
-        return val * (r * r);
-    }
-
-    // General view: contributions are 0 unless w > 0 and the position is
-    // strictly inside (-1, W) x (-1, H), i.e. (0, W+1) x (0, H+1) padded.
-    __device__ __forceinline__ float contrib_guarded(const View& vw, float u, float v, float w) const
-    {
-        const float r = __builtin_amdgcn_rcpf(w);
-        float s = fmaf(u, r, 1.0f), t = fmaf(v, r, 1.0f);
-        const bool ok = (w > 0.0f) & (s > 0.0f) & (s < (float)(W + 1)) & (t > 0.0f) &
-                        (t < (float)(H + 1));
-        s = ok ? s : 0.0f;
-        t = ok ? t : 0.0f;
-        const int i0 = (int)s, j0 = (int)t;
-        const float fx = __builtin_amdgcn_fractf(s);
-        const float fy = __builtin_amdgcn_fractf(t);
-        float a, b, c, d;
-        taps(vw, i0, j0, a, b, c, d);
+        taps_row(vw, i0, j0, a, b);
+        taps_row(vw, i0, j0 + 1, c, d);
         const float top = fmaf(fx, b - a, a);
         const float bot = fmaf(fx, d - c, c);
         const float val = fmaf(fy, bot - top, top);
@@ -273,7 +193,10 @@ struct PatchSource {
         }
     }
 
-    // See PaddedSource::contrib_safe: positions clamped into [0, W+1] x [0, H+1].
+    // Safe view (every voxel of the box has w >= 1e-4 * max w > 0): the
+    // position is clamped into the bordered frame [0, W+1] x [0, H+1]; a
+    // clamped position lands on border patches whose value there is exactly 0,
+    // as the zero-extended image would give.
     __device__ __forceinline__ float contrib_safe(const View& vw, float u, float v, float w) const
     {
         const float r = __builtin_amdgcn_rcpf(w);
@@ -592,34 +515,6 @@ __global__ void cull_kernel(const ViewConst* __restrict__ vc, int n_views, Box b
     out[id] = bits;
 }
 
-// ---------------------------------------------------------------------------
-// Zero-padded staging copy (Sec. 5.1.1): one thread per padded element.
-// ---------------------------------------------------------------------------
-template <Dtype DT>
-__global__ __launch_bounds__(256) void pad_kernel(const void* __restrict__ proj, int W, int H,
-                                                  uint32_t* __restrict__ out)
-{
-    const int Wp = W + 3, Hp = H + 3;
-    const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int r = (int)blockIdx.y;
-    const int k = (int)blockIdx.z;
-    if (c >= Wp || r >= Hp) return;
-    const int i = c - 1, j = r - 1;
-    const bool row_ok = (j >= 0) & (j < H);
-    uint32_t v = 0;
-    if constexpr (DT == Dtype::F32) {
-        const float* img = (const float*)proj + (size_t)k * W * H;
-        if (row_ok && i >= 0 && i < W) v = __builtin_bit_cast(uint32_t, img[(size_t)j * W + i]);
-    } else {
-        const uint16_t* img = (const uint16_t*)proj + (size_t)k * W * H;
-        uint32_t lo = 0, hi = 0;
-        if (row_ok && i >= 0 && i < W) lo = img[(size_t)j * W + i];
-        if (row_ok && i + 1 >= 0 && i + 1 < W) hi = img[(size_t)j * W + i + 1];
-        v = lo | (hi << 16);
-    }
-    out[((size_t)k * Hp + r) * Wp + c] = v;
-}
-
 template <typename T>
 __device__ __forceinline__ float pixel_f32(const T* img, int W, int H, int i, int j)
 {
@@ -753,19 +648,6 @@ hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, boo
     return hipGetLastError();
 }
 
-hipError_t launch_pad(Dtype dt, const void* proj, int W, int H, int n, void* padded, hipStream_t s)
-{
-    const dim3 block(256, 1, 1);
-    const dim3 grid((unsigned)((W + 3 + 255) / 256), (unsigned)(H + 3), (unsigned)n);
-    uint32_t* out = (uint32_t*)padded;
-    switch (dt) {
-    case Dtype::F32: hipLaunchKernelGGL(pad_kernel<Dtype::F32>, grid, block, 0, s, proj, W, H, out); break;
-    case Dtype::F16: hipLaunchKernelGGL(pad_kernel<Dtype::F16>, grid, block, 0, s, proj, W, H, out); break;
-    case Dtype::BF16: hipLaunchKernelGGL(pad_kernel<Dtype::BF16>, grid, block, 0, s, proj, W, H, out); break;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, hipStream_t s)
 {
     const dim3 block(256, 1, 1);
@@ -844,19 +726,17 @@ hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float
         default: return hipErrorInvalidValue;
         }
     }
-    if (tile_x != 64) return hipErrorInvalidValue;
-    if (layout == Layout::Pairs) {
+    {
+#define BP_CHECKED(T)                                                                                           \
+    (tile_x == 16 ? launch_zu<CheckedSource<T>, false, 16>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s)  \
+                  : launch_zu<CheckedSource<T>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s))
+        if (tile_x != 16 && tile_x != 64) return hipErrorInvalidValue;
         switch (dt) {
-        case Dtype::F32: return launch_zu<PaddedSource<Dtype::F32>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
-        case Dtype::F16: return launch_zu<PaddedSource<Dtype::F16>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
-        case Dtype::BF16: return launch_zu<PaddedSource<Dtype::BF16>, true, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
+        case Dtype::F32: return BP_CHECKED(float);
+        case Dtype::F16: return BP_CHECKED(__half);
+        case Dtype::BF16: return BP_CHECKED(uint16_t);
         }
-    } else {
-        switch (dt) {
-        case Dtype::F32: return launch_zu<CheckedSource<float>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
-        case Dtype::F16: return launch_zu<CheckedSource<__half>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
-        case Dtype::BF16: return launch_zu<CheckedSource<uint16_t>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s);
-        }
+#undef BP_CHECKED
     }
     return hipErrorInvalidValue;
 }

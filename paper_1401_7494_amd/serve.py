@@ -253,3 +253,51 @@ class GpuExecutor:
             for ctx in pool:
                 ctx.close()
         self._free_ctx.clear()
+
+
+def main(argv=None):
+    """Serve a seeded Poisson stream on the GPU: ``python -m paper_1401_7494_amd.serve``.
+
+    First every request is offered at time 0 to measure back-to-back capacity,
+    then the stream is replayed with Poisson arrivals at ``load`` times that
+    capacity.  Prints one JSON line per phase.
+    """
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="continuous-batching serving run on one GPU")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=1405)
+    ap.add_argument("--budget-gib", type=float, default=200.0)
+    ap.add_argument("--max-inflight", type=int, default=8)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of measured capacity")
+    ap.add_argument("--rate", type=float, default=0.0, help="arrival rate (requests/s); 0 = load x capacity")
+    args = ap.parse_args(argv)
+    budget = int(args.budget_gib * GIB)
+    base = synth.poisson_requests(args.requests, 1.0, args.seed)
+    phases = []
+    if not args.rate:
+        burst = [synth.Request(r.rid, 0.0, r.L, r.n_views, r.dtype, r.phantom_seed) for r in base]
+        ex = GpuExecutor()
+        rep = Server(ex, budget, args.max_inflight).run(burst)
+        ex.close()
+        cap = len(rep.completed) / rep.makespan_s
+        s = rep.summary()
+        s.update(phase="back_to_back", capacity_rps=cap)
+        print(json.dumps(s), flush=True)
+        phases.append(s)
+        rate = args.load * cap
+    else:
+        rate = args.rate
+    stream = synth.poisson_requests(args.requests, rate, args.seed)
+    ex = GpuExecutor()
+    rep = Server(ex, budget, args.max_inflight).run(stream)
+    ex.close()
+    s = rep.summary()
+    s.update(phase="poisson", rate_rps=rate, budget_gib=args.budget_gib, max_inflight=args.max_inflight)
+    print(json.dumps(s), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

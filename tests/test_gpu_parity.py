@@ -47,22 +47,24 @@ def small_inputs():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("path,k", [("plain", 1), ("fused", 4), ("fused", 13), ("fused", 32)])
+@pytest.mark.parametrize("path,k,tx", [("plain", 1, 64), ("plain", 1, 16), ("fused", 4, 16), ("fused", 13, 8),
+                                       ("fused", 32, 64)])
 @pytest.mark.parametrize("zu", [1, 2, 4, 8])
-def test_parity_small_ragged(small_inputs, dtype, path, k, zu):
+def test_parity_small_ragged(small_inputs, dtype, path, k, tx, zu):
     proj32, P32 = small_inputs
     proj = proj32.to(gc.TORCH_DTYPE[dtype])
     origin = _box_origin(BOX, VS)
-    got = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path=path, k=k, zu=zu)
+    got = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path=path, k=k, zu=zu, tx=tx)
     ref = _oracle_box(proj, P32, BOX, VS, origin)
     err = gc.error_stats(got, ref)
-    print(f"\n{dtype} {path} K={k} ZU={zu}: {err}")
+    print(f"\n{dtype} {path} K={k} ZU={zu} TX={tx}: {err}")
     assert np.abs(ref).max() > 0
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
 
 
-@pytest.mark.parametrize("path,zu", [("plain", 1), ("plain", 8), ("fused", 1), ("fused", 4), ("fused", 8)])
-def test_orthographic_identity_is_bit_exact(path, zu):
+@pytest.mark.parametrize("path,zu,tx", [("plain", 1, 64), ("plain", 8, 16), ("fused", 1, 16), ("fused", 4, 8),
+                                         ("fused", 8, 64)])
+def test_orthographic_identity_is_bit_exact(path, zu, tx):
     """w = 1 and integer positions: every voxel (x, y, z) is exactly sum_k I_k[y][x]."""
     from oracle import closed
 
@@ -70,7 +72,7 @@ def test_orthographic_identity_is_bit_exact(path, zu):
     origin = (-65.0, -65.0, -65.0)
     proj = synth.integer_images((n, H, W), seed=3)
     P = closed.orthographic_matrices(n, vs, origin).astype(np.float32)
-    got = gc.run_gpu(proj, P, (L, L, L), vs, origin, path=path, k=4, zu=zu)
+    got = gc.run_gpu(proj, P, (L, L, L), vs, origin, path=path, k=4, zu=zu, tx=tx)
     want = closed.orthographic_volume(proj.numpy(), L)
     assert np.array_equal(got.astype(np.float64), want)
 
@@ -198,7 +200,9 @@ def test_plan_reports_choices():
         assert p.path in ("plain", "fused") and p.z_unroll in (1, 2, 4, 8)
         ctx.set_tuning("plain", 0, 4, 16)
         p = ctx.plan(512, 512, 512, 496)
-        assert (p.path, p.views_per_pass, p.z_unroll, p.tile_x) == ("plain", 1, 4, 64)
+        assert (p.path, p.views_per_pass, p.z_unroll, p.tile_x) == ("plain", 1, 4, 16)
+        ctx.set_tuning("plain", 0, 4, 8)
+        assert ctx.plan(512, 512, 512, 496).tile_x == 64
         ctx.set_tuning("fused", 500, 2, 8)
         p = ctx.plan(64, 64, 64, 496)
         assert (p.views_per_pass, p.tile_x) == (496, 8)
@@ -374,3 +378,18 @@ def test_stream_checkpoint_resume_is_bit_exact(small_inputs, k):
     ckpt = np.array(ckpt, copy=True)  # the checkpoint lives on the host
     resumed = gc.run_gpu(proj32[cut:], P32[cut:], BOX, VS, origin, path="fused", k=k, zu=8, init=ckpt)
     assert np.array_equal(resumed, whole)
+
+
+def test_parity_l1024_sampled():
+    """L=1024 (voxel 0.25 mm, 4 GiB volume), 496 views streamed in passes: every 16th voxel
+    per axis (64^3 voxels spread over the volume) against the oracle."""
+    wl = synth.WORKLOADS["fdk_l1024_v496_f32"]
+    v = wl.volume
+    proj = gc.full_projections(wl.phantom_seed)
+    P32 = gc.product_matrices(wl.scanner)
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin)
+    xyz = strided_sample(v.L, 16, 7)
+    ref = oracle.backproject_points(proj.cpu().numpy(), P32.astype(np.float64), v.voxel_size, v.origin, xyz)
+    err = gc.error_stats(got[xyz[:, 2], xyz[:, 1], xyz[:, 0]], ref)
+    print(f"\nL=1024 uniform sample: {err}")
+    assert err["rel_l2"] <= gc.REL_L2_TOL, err

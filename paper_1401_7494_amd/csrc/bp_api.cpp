@@ -161,7 +161,7 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     p.path = ctx->path_override != BP_PATH_AUTO ? ctx->path_override : ctx->cfg.path;
     if (p.path == BP_PATH_AUTO) p.path = BP_PATH_FUSED;
     p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
-    if (p.k <= 0) p.k = 32;
+    if (p.k <= 0) p.k = ctx->cfg.proj_dtype == BP_F32 ? 32 : 64;  // 8-byte staging records halve the pass footprint
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;
     p.zu = ctx->zu_override > 0 ? ctx->zu_override : ctx->cfg.z_unroll;

@@ -13,6 +13,9 @@ Contents
               them.
   closed      closed-form back projections (constant, affine, impulse images,
               orthographic identity) used to pin the oracle.
+  fdk         FP64 cosine weighting and Ram-Lak row filtering: the pre-processing
+              that turns raw projections into the filtered, weighted input of
+              the back projection.
 
 Every function cites the passage of Hofmann, Treibig, Hager and Wellein,
 "Comparing the Performance of Different x86 SIMD Instruction Sets for a
@@ -20,7 +23,7 @@ Medical Imaging Application on Modern Multi- and Manycore Chips" (WPMVP'14)
 that it follows.
 """
 from .bp import backproject, backproject_points, interpolate, tent_interpolate, load_library, build_library
-from . import geometry, closed
+from . import geometry, closed, fdk
 
 __all__ = [
     "backproject",
@@ -31,4 +34,5 @@ __all__ = [
     "build_library",
     "geometry",
     "closed",
+    "fdk",
 ]

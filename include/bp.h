@@ -201,6 +201,67 @@ const char *bp_last_error(bp_ctx ctx);
 /* Library version, "major.minor.patch". */
 const char *bp_version(void);
 
+/* ------------------------------------------------------------------------
+ * FDK pre-processing: raw projections -> the filtered, weighted projections
+ * that bp_backproject consumes (Sec. 4 describes the benchmark input as
+ * filtered and weighted; the paper does not spell the two steps out, so
+ * this library uses the Feldkamp-Davis-Kress pre-processing):
+ *
+ *   c[j][i]    = SDD / sqrt(SDD^2 + u_i^2 + v_j^2)        cosine weight,
+ *                u_i = (i - (W-1)/2) pitch, v_j = (j - (H-1)/2) pitch (mm)
+ *   q[k][j][i] = tau * sum_{m=0}^{W-1} h(i - m) c[j][m] p[k][j][m]
+ *                (linear convolution along each detector row: no samples
+ *                beyond the row), tau = pitch * SID / SDD, and h the discrete
+ *                Ram-Lak kernel of Kak and Slaney: h(0) = 1/(4 tau^2),
+ *                h(odd n) = -1/(pi n tau)^2, h(even n != 0) = 0.
+ *
+ * Arithmetic is FP64 (by FFT of length 4096, so det_width <= 2048); each
+ * output is rounded once to FP32, and from there to FP16 or BF16 (round to
+ * nearest even) if asked.
+ *
+ * Layouts: raw and filtered are n_views x det_height x det_width, pixel (i, j)
+ * of view k at (k * det_height + j) * det_width + i, DEVICE pointers on the
+ * handle's device; raw is FP32, filtered is out_dtype.  The caller owns both;
+ * they must stay valid until the work on `stream` has completed.  filtered
+ * may be the same pointer as raw for FP32 output (in place); any other
+ * overlap is an error.  A handle owns two small read-only device tables
+ * (96 KiB), so concurrent calls on one handle are safe.
+ *
+ * Errors as above: checks run before anything is enqueued; a call that
+ * returns anything but BP_OK has enqueued nothing.
+ * ------------------------------------------------------------------------ */
+typedef struct bp_fdk_s *bp_fdk;
+
+typedef struct {
+    int device;     /* HIP device index */
+    int det_width;  /* W: columns per row, 1 <= W <= 2048 (else BP_ERR_UNSUPPORTED) */
+    int det_height; /* H: rows per view, >= 1 */
+    double pitch;   /* detector pixel pitch, mm, > 0 */
+    double sid;     /* source to isocentre distance, mm, > 0 */
+    double sdd;     /* source to detector distance, mm, > 0 */
+} bp_fdk_config;
+
+/* RabbitCT-like defaults: device 0, 1248 x 960 pixels of 0.32 mm, SID 800, SDD 1200. */
+void bp_fdk_config_default(bp_fdk_config *cfg);
+
+/* Allocate the handle and build its tables (synchronously).  On failure
+ * *out is NULL: BP_ERR_INVALID_ARG (bad config), BP_ERR_UNSUPPORTED (width),
+ * BP_ERR_DEVICE, BP_ERR_OUT_OF_MEMORY or BP_ERR_LAUNCH. */
+bp_status bp_fdk_create(const bp_fdk_config *cfg, bp_fdk *out);
+
+/* Weight and filter n_views raw views into `filtered`, asynchronously on
+ * `stream` (a hipStream_t; NULL = the null stream).  out_dtype: BP_F32,
+ * BP_F16 or BP_BF16. */
+bp_status bp_fdk_filter(bp_fdk f, const float *raw, void *filtered, bp_dtype out_dtype, int n_views,
+                        void *stream);
+
+/* Waits for the device, then frees the handle.  bp_fdk_destroy(NULL) is a no-op. */
+bp_status bp_fdk_destroy(bp_fdk f);
+
+/* Description of the last failed call on the handle. */
+const char *bp_fdk_last_error(bp_fdk f);
+
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,17 @@ class BpConfig(ctypes.Structure):
     ]
 
 
+class BpFdkConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", _c_int),
+        ("det_width", _c_int),
+        ("det_height", _c_int),
+        ("pitch", _c_double),
+        ("sid", _c_double),
+        ("sdd", _c_double),
+    ]
+
+
 SIGNATURES = {
     "bp_config_default": (None, [ctypes.POINTER(BpConfig)]),
     "bp_create": (_c_int, [ctypes.POINTER(BpConfig), ctypes.POINTER(_vp)]),
@@ -56,6 +67,11 @@ SIGNATURES = {
     "bp_status_string": (ctypes.c_char_p, [_c_int]),
     "bp_last_error": (ctypes.c_char_p, [_vp]),
     "bp_version": (ctypes.c_char_p, []),
+    "bp_fdk_config_default": (None, [ctypes.POINTER(BpFdkConfig)]),
+    "bp_fdk_create": (_c_int, [ctypes.POINTER(BpFdkConfig), ctypes.POINTER(_vp)]),
+    "bp_fdk_filter": (_c_int, [_vp, _vp, _vp, _c_int, _c_int, _vp]),
+    "bp_fdk_destroy": (_c_int, [_vp]),
+    "bp_fdk_last_error": (ctypes.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -232,6 +248,72 @@ class Context:
         st = lib().bp_backproject_box(self._h, volume.data_ptr(), nx, ny, nz, projections.data_ptr(),
                                       matrices.data_ptr(), n, float(voxel_size), o, _stream_handle(stream, self.device))
         self._check(st, "bp_backproject_box")
+
+
+class FdkFilter:
+    """FDK pre-processing on one device for one detector geometry (``bp_fdk_*``).
+
+    ``filter(raw, out_dtype)`` weights and ramp-filters raw projections
+    (N, H, W) FP32 into a new tensor of ``out_dtype`` ("f32", "f16", "bf16"),
+    or into ``out`` (which may be ``raw`` itself for FP32).
+    """
+
+    def __init__(self, det_width=1248, det_height=960, pitch=0.32, sid=800.0, sdd=1200.0, device=0):
+        L = lib()
+        cfg = BpFdkConfig()
+        L.bp_fdk_config_default(ctypes.byref(cfg))
+        cfg.device, cfg.det_width, cfg.det_height = int(device), int(det_width), int(det_height)
+        cfg.pitch, cfg.sid, cfg.sdd = float(pitch), float(sid), float(sdd)
+        h = _vp()
+        st = L.bp_fdk_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != BP_OK:
+            raise BPError(st, f"bp_fdk_create: {status_string(st)}")
+        self._h = h
+        self.det_width, self.det_height, self.device = det_width, det_height, device
+
+    @classmethod
+    def for_scanner(cls, scanner, device=0):
+        return cls(scanner.W, scanner.H, scanner.pitch, scanner.sid, scanner.sdd, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bp_fdk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def last_error(self) -> str:
+        return lib().bp_fdk_last_error(self._h).decode()
+
+    def filter(self, raw, out_dtype="f32", out=None, stream=None):
+        import torch
+
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[out_dtype]
+        _need(raw, torch.float32, "raw", 3)
+        if raw.shape[1:] != (self.det_height, self.det_width):
+            raise ValueError(f"raw must be (N, {self.det_height}, {self.det_width})")
+        if raw.device.index != self.device:
+            raise ValueError("raw is not on the filter's device")
+        if out is None:
+            out = torch.empty(raw.shape, dtype=tdt, device=raw.device)
+        _need(out, tdt, "out", 3)
+        if out.shape != raw.shape or out.device != raw.device:
+            raise ValueError("out must match raw in shape and device")
+        st = lib().bp_fdk_filter(self._h, raw.data_ptr(), out.data_ptr(), DTYPES[out_dtype], raw.shape[0],
+                                 _stream_handle(stream, self.device))
+        if st != BP_OK:
+            raise BPError(st, f"bp_fdk_filter: {status_string(st)}: {self.last_error()}")
+        return out
 
 
 def _need(t, dtype, name, ndim):

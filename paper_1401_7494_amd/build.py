@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbp.so")
-SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_geometry.cpp"]
+SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_geometry.cpp", "fdk_kernels.hip", "fdk_api.cpp"]
 # The seeded input generator's GPU kernels: a library of their own, not linked into libbp.so.
 SYNTH_LIB = os.path.join(HERE, "libbpsynth.so")
 SYNTH_SOURCES = ["synth_kernels.hip"]

@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cull", action="store_true", help="time without the clipping mask")
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
+    ap.add_argument("--lds-taps", action="store_true", help="stage each tile's footprint through LDS")
     ap.add_argument("--cpu-block", type=int, default=160, help="edge of the centre block the oracle times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -92,7 +93,7 @@ def log(msg):
 
 
 def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
-              no_column=False, order="region", region_ax=0):
+              no_column=False, order="region", region_ax=0, lds_taps=False):
     path, dt = form.split("_")
     proj = proj_by_dtype[dt]
     n, H, W = proj.shape
@@ -102,7 +103,7 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
     stream = torch.cuda.current_stream(dev)
     ctx = bp.Context(W, H, dt)
     ctx.set_tuning(path, k, zu, tx)
-    ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax)
+    ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax, lds_taps=lds_taps)
     plan = ctx.plan(L, L, L, n)
     for _ in range(warmup):
         ctx.backproject(vol, proj, P, vol_cfg.voxel_size, vol_cfg.origin, stream)
@@ -173,7 +174,7 @@ def main():
     results = {}
     for form in forms:
         r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
-                      args.no_cull, args.no_column, args.order, args.region_ax)
+                      args.no_cull, args.no_column, args.order, args.region_ax, args.lds_taps)
         ms = r["step_ms"]
         r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9

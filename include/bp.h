@@ -140,6 +140,10 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     compact FP16 coefficients (8 bytes, scaled per view by a
  *                     power of two; adds the rounding of the pixel differences
  *                     to FP16, ~2^-11 relative)
+ *   BP_OPT_LDS_TAPS   fused path: for every (block tile, view) copy the tile's
+ *                     footprint of the staging buffer into LDS with coalesced row
+ *                     loads and read the taps from there (results bit-identical;
+ *                     the clipping mask is then part of the footprint table)
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of
@@ -157,6 +161,7 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_XCD_REGION_SHIFT 5
 #define BP_OPT_XCD_REGION_MASK (15 << BP_OPT_XCD_REGION_SHIFT)
 #define BP_OPT_XCD_REGION(ax) ((ax) << BP_OPT_XCD_REGION_SHIFT)
+#define BP_OPT_LDS_TAPS (1 << 9)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */

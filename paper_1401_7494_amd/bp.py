@@ -184,10 +184,11 @@ class Context:
     OPT_WIDE_STAGING = 8
     OPT_PLAIN_ORDER = 16
     OPT_XCD_REGION_SHIFT = 5
+    OPT_LDS_TAPS = 1 << 9
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
-                    order: str = "region", region_ax: int = 0):
+                    order: str = "region", region_ax: int = 0, lds_taps: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
         projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
         each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices")."""
@@ -200,6 +201,8 @@ class Context:
         elif order != "region":
             raise ValueError(f"order must be one of {self.ORDERS}")
         flags |= int(region_ax) << self.OPT_XCD_REGION_SHIFT
+        if lds_taps:
+            flags |= self.OPT_LDS_TAPS
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     KERNELS = {"backproject": 0, "pad": 1, "views": 2}

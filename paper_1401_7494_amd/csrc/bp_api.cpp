@@ -27,6 +27,8 @@ struct bp_ctx_s {
     size_t cull_cap = 0;  // bytes
     void* d_scale = nullptr;  // compact staging: per-view max |pixel| bits, then 2^-e scales
     size_t scale_cap = 0;
+    void* d_fp = nullptr;  // LDS-staged taps: footprint table of one pass
+    size_t fp_cap = 0;
     int options = 0;      // BP_OPT_* flags
     // overrides set by bp_set_tuning (0 = tuned)
     bp_path path_override = BP_PATH_AUTO;
@@ -260,6 +262,7 @@ bp_status bp_destroy(bp_ctx ctx)
             if (ctx->d_pad && hipFree(ctx->d_pad) != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_cull && hipFree(ctx->d_cull) != hipSuccess) st = BP_ERR_DEVICE;
             if (ctx->d_scale && hipFree(ctx->d_scale) != hipSuccess) st = BP_ERR_DEVICE;
+            if (ctx->d_fp && hipFree(ctx->d_fp) != hipSuccess) st = BP_ERR_DEVICE;
         }
     }
     delete ctx;
@@ -297,7 +300,7 @@ bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
-                    BP_OPT_XCD_REGION_MASK))
+                    BP_OPT_XCD_REGION_MASK | BP_OPT_LDS_TAPS))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
     if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
@@ -359,13 +362,20 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     DeviceGuard g(ctx->cfg.device);
     if (!g.ok) return fail(ctx, BP_ERR_DEVICE, "cannot select the context's device");
 
-    bp_status st = ensure(ctx, reinterpret_cast<void**>(&ctx->d_views), &ctx->views_cap,
-                          sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
-    if (st != BP_OK) return st;
-    if (ctx->views_cap < sizeof(bp::ViewConst) * (size_t)n_views) return BP_ERR_OUT_OF_MEMORY;
     bp::Layout layout = plan.path == BP_PATH_FUSED ? bp::Layout::Patch : bp::Layout::Checked;
     if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
         layout = bp::Layout::Patch16;
+    // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
+    const bool lds = layout != bp::Layout::Checked && (ctx->options & BP_OPT_LDS_TAPS) && W + 2 < 65536 &&
+                     H + 2 < 65536;
+    const bool culled = layout != bp::Layout::Checked && !lds && !(ctx->options & BP_OPT_NO_CULL);
+    const long tiles = bp::n_tiles(nx, ny, nz, plan.zu, plan.tx);
+    const int words = bp::cull_words(n_views);
+
+    // all scratch first: a call that fails here has enqueued nothing
+    bp_status st = ensure(ctx, reinterpret_cast<void**>(&ctx->d_views), &ctx->views_cap,
+                          sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
+    if (st != BP_OK) return st;
     if (layout != bp::Layout::Checked) {
         st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, bp::staged_view_bytes(layout, W, H) * (size_t)plan.k,
                     "staged projections");
@@ -375,6 +385,14 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             if (st != BP_OK) return st;
         }
     }
+    if (culled) {
+        st = ensure(ctx, &ctx->d_cull, &ctx->cull_cap, (size_t)tiles * (size_t)words * 4u, "clipping mask");
+        if (st != BP_OK) return st;
+    }
+    if (lds) {
+        st = ensure(ctx, &ctx->d_fp, &ctx->fp_cap, (size_t)tiles * (size_t)plan.k * sizeof(uint2), "footprints");
+        if (st != BP_OK) return st;
+    }
 
     const bool column_ok = !(ctx->options & BP_OPT_NO_COLUMN);
     if (timed(ctx, 2, s, [&] { return bp::launch_prep_views(matrices, n_views, box, column_ok, ctx->d_views, s); }) !=
@@ -383,11 +401,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
 
     // Clipping mask for the fused path: skip bits per (tile, view).
     bp::Cull cull{nullptr, 0, 0};
-    if (layout != bp::Layout::Checked && !(ctx->options & BP_OPT_NO_CULL)) {
-        const int words = bp::cull_words(n_views);
-        const size_t need = (size_t)bp::n_tiles(nx, ny, nz, plan.zu, plan.tx) * (size_t)words * 4u;
-        st = ensure(ctx, &ctx->d_cull, &ctx->cull_cap, need, "clipping mask");
-        if (st != BP_OK) return st;
+    if (culled) {
         if (timed(ctx, 2, s, [&] {
                 return bp::launch_cull(ctx->d_views, n_views, box, plan.zu, plan.tx, W, H, (uint32_t*)ctx->d_cull, s);
             }) != hipSuccess)
@@ -416,14 +430,23 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                            : bp::launch_patch(dt, src_views, W, H, kc, ctx->d_pad, s);
             });
             if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
+            uint2* fp = lds ? static_cast<uint2*>(ctx->d_fp) : nullptr;
+            if (lds) {
+                e = timed(ctx, 2, s, [&] {
+                    return bp::launch_footprint(ctx->d_views + k0, kc, box, plan.zu, plan.tx, W, H,
+                                                bp::kStageRecords, fp, s);
+                });
+                if (e != hipSuccess)
+                    return fail(ctx, BP_ERR_LAUNCH, std::string("footprint kernel: ") + hipGetErrorString(e));
+            }
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
-                                              ctx->d_pad, W, H, cull, xcd_order, inv_scale, s);
+                                              ctx->d_pad, W, H, cull, xcd_order, inv_scale, fp, s);
             });
         } else {
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
-                                              src_views, W, H, cull, xcd_order, nullptr, s);
+                                              src_views, W, H, cull, xcd_order, nullptr, nullptr, s);
             });
         }
         if (e != hipSuccess)

@@ -69,9 +69,26 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 // tile_x: columns along x per block (64, 32, 16 or 8; the plain path takes
 // 16 or 64); a block covers tile_x x (256 / tile_x)
 // columns.  xcd_order: deal contiguous z-ranges of tiles to the 8 XCDs.
+// footprints (patch layouts only; null = read the taps directly): the pass's
+// footprint table from launch_footprint, [tile][view] -- the taps are then
+// staged through LDS.
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
-                              const Cull& cull, int xcd_order, const float* inv_scale, hipStream_t s);
+                              const Cull& cull, int xcd_order, const float* inv_scale, const uint2* footprints,
+                              hipStream_t s);
+
+// Patch records a block of the staged pass holds one view's footprint in (LDS):
+// footprints of up to 64 columns by 32 rows.
+constexpr int kStageRecords = 2048;
+// Footprint table entries {x, y}: y == kFootprintSkip -> the tile misses the
+// detector in that view; y == kFootprintDirect -> read that view's taps
+// directly; otherwise x = cmin | rmin << 16, y = fw | fh << 16.
+constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
+
+
+// Footprint table of one pass: n views (view constants vc[0, n)), every tile.
+hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
+                            int cap, uint2* out, hipStream_t s);
 
 // Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
 inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)

@@ -37,6 +37,9 @@ namespace {
 
 constexpr int kBlock = 256;  // threads per block: 4 wavefronts
 constexpr int kXcds = 8;     // MI355X: 8 XCDs, consecutive workgroups go to consecutive XCDs
+// LDS-staged taps: one footprint row per wave and slot, one column per lane
+constexpr int kStageSlots = 8;
+constexpr int kStageMaxWidth = 64, kStageMaxHeight = 4 * kStageSlots;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {
@@ -159,13 +162,29 @@ struct PatchSource {
         return v;
     }
 
+    using Rec = f32x4_t;
+
+    __device__ __forceinline__ Rec load(const View& vw, int idx) const
+    {
+        return struct_buffer_load_f32x4(vw.rs, idx, 0, 0, 0);
+    }
+
+    // Part 3 on one patch: a + fx dx + fy (dy + fx dxy).
+    static __device__ __forceinline__ float eval(const Rec& q, float fx, float fy)
+    {
+        return fmaf(fx, q.y, fmaf(fy, fmaf(fx, q.w, q.z), q.x));
+    }
+
+    // 1/w^2 from r = 1/w: as the column branch and the per-voxel branch form it.
+    __device__ __forceinline__ float weight_column(const View&, float r) const { return r * r; }
+    __device__ __forceinline__ float weight_voxel(const View&, float r) const { return r * r; }
+
     // Patch value at padded column c0 + fx, padded row t (t >= 0, so truncation is floor).
     __device__ __forceinline__ float patch_at(const View& vw, int c0, float fx, float t) const
     {
         const int r0 = (int)t;
         const float fy = __builtin_amdgcn_fractf(t);
-        const f32x4_t q = struct_buffer_load_f32x4(vw.rs, __mul24(r0, cols()) + c0, 0, 0, 0);
-        return fmaf(fx, q.y, fmaf(fy, fmaf(fx, q.w, q.z), q.x));
+        return eval(load(vw, __mul24(r0, cols()) + c0), fx, fy);
     }
 
     __device__ __forceinline__ float patch(const View& vw, float s, float t) const
@@ -254,12 +273,26 @@ struct Patch16Source {
         return v;
     }
 
+    using Rec = f16x4_t;
+
+    __device__ __forceinline__ Rec load(const View& vw, int idx) const
+    {
+        return struct_buffer_load_f16x4(vw.rs, idx, 0, 0, 0);
+    }
+
+    static __device__ __forceinline__ float eval(const Rec& q, float fx, float fy)
+    {
+        return fmaf(fx, (float)q.y, fmaf(fy, fmaf(fx, (float)q.w, (float)q.z), (float)q.x));
+    }
+
+    __device__ __forceinline__ float weight_column(const View& vw, float r) const { return r * r * vw.inv; }
+    __device__ __forceinline__ float weight_voxel(const View& vw, float r) const { return r * (r * vw.inv); }
+
     __device__ __forceinline__ float patch_at(const View& vw, int c0, float fx, float t) const
     {
         const int r0 = (int)t;
         const float fy = __builtin_amdgcn_fractf(t);
-        const f16x4_t q = struct_buffer_load_f16x4(vw.rs, __mul24(r0, cols()) + c0, 0, 0, 0);
-        return fmaf(fx, (float)q.y, fmaf(fy, fmaf(fx, (float)q.w, (float)q.z), (float)q.x));
+        return eval(load(vw, __mul24(r0, cols()) + c0), fx, fy);
     }
 
     __device__ __forceinline__ float patch(const View& vw, float s, float t) const
@@ -275,7 +308,7 @@ struct Patch16Source {
         const float s = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
         const int c0 = (int)s;
         const float fx = __builtin_amdgcn_fractf(s);
-        const float r2 = r * r * vw.inv;
+        const float r2 = weight_column(vw, r);
         const float dt = p12 * r;
         const float tb = fmaf(vxy, r, 1.0f);
 #pragma unroll
@@ -290,7 +323,7 @@ struct Patch16Source {
         const float r = __builtin_amdgcn_rcpf(w);
         const float s = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
         const float t = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
-        return patch(vw, s, t) * (r * (r * vw.inv));
+        return patch(vw, s, t) * weight_voxel(vw, r);
     }
 
     __device__ __forceinline__ float contrib_guarded(const View& vw, float u, float v, float w) const
@@ -341,15 +374,9 @@ struct has_column<Patch16Source> {
 // cull: optional per-(tile, view) skip bits, `cull_words` words per tile,
 // bit (kbase + k) set when the whole tile projects off the detector in view k
 // of this pass.  Skipped views contribute exact zeros.
-template <class Src, int ZU, bool PADDED, int TX>
-__global__ __launch_bounds__(kBlock) void backproject_kernel(
-    float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
-    const uint32_t* __restrict__ cull, int cull_words, int kbase, int xcd_order)
+__device__ __forceinline__ int tile_of_block(int b, int gx, int gy, int n_tiles, int xcd_order)
 {
-    constexpr int TY = kBlock / TX;
-    const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
-    const int n_tiles = gx * gy * gz;
-    int tile = (int)blockIdx.x;
+    int tile = b;
     if (xcd_order == 1) {
         const int per = (n_tiles + kXcds - 1) / kXcds;
         tile = (tile % kXcds) * per + tile / kXcds;
@@ -365,6 +392,18 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
         const int bx_ = (xcd % ax) * rx + r % rx, by_ = (xcd / ax) * ry + r / rx;
         tile = (layer * gy + by_) * gx + bx_;
     }
+    return tile;
+}
+
+template <class Src, int ZU, bool PADDED, int TX>
+__global__ __launch_bounds__(kBlock) void backproject_kernel(
+    float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
+    const uint32_t* __restrict__ cull, int cull_words, int kbase, int xcd_order)
+{
+    constexpr int TY = kBlock / TX;
+    const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
+    const int n_tiles = gx * gy * gz;
+    const int tile = tile_of_block((int)blockIdx.x, gx, gy, n_tiles, xcd_order);
     if (tile >= n_tiles) return;  // padding blocks of the XCD order (no barriers in this kernel)
     const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
     int x = bx * TX + (int)threadIdx.x % TX;
@@ -434,6 +473,232 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// The fused pass with the taps staged through LDS.  For each view of the pass
+// the block first copies its tile's footprint -- the rectangle of patch
+// records that any voxel of the tile can read, from the footprint table --
+// from the staging buffer into LDS with coalesced row loads, then every
+// voxel reads its one patch record from LDS.  The positions are clamped to
+// the footprint instead of the bordered frame; the footprint holds every
+// position the tile's voxels reach with a margin (see footprint_kernel), so
+// the clamp only ever acts at the detector border, exactly as in the direct
+// pass, and the results are bit-identical to it.  Views whose footprint does
+// not fit the LDS buffer, and guarded views, read their taps directly.
+// ---------------------------------------------------------------------------
+template <class Src, int ZU, int TX>
+__global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
+    float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
+    const uint2* __restrict__ fp, int xcd_order)
+{
+    using Rec = typename Src::Rec;
+    static_assert(kStageMaxWidth * kStageMaxHeight == kStageRecords, "LDS stage shape");
+    __shared__ Rec lds[kStageRecords];
+    constexpr int TY = kBlock / TX;
+    const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
+    const int n_tiles = gx * gy * gz;
+    const int tile = tile_of_block((int)blockIdx.x, gx, gy, n_tiles, xcd_order);
+    if (tile >= n_tiles) return;  // whole block: before any barrier
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    int x = bx * TX + (int)threadIdx.x % TX;
+    int y = by * TY + (int)threadIdx.x / TX;
+    const int z0 = bz * ZU;
+    const bool in_xy = (x < box.nx) & (y < box.ny);
+    x = min(x, box.nx - 1);
+    y = min(y, box.ny - 1);
+    const float X = fmaf(box.vs, (float)x, box.ox);
+    const float Y = fmaf(box.vs, (float)y, box.oy);
+    float Z[ZU], acc[ZU];
+#pragma unroll
+    for (int i = 0; i < ZU; ++i) {
+        Z[i] = fmaf(box.vs, (float)min(z0 + i, box.nz - 1), box.oz);
+        acc[i] = 0.0f;
+    }
+    const uint2* fp_row = fp + (size_t)tile * n_views;
+    // Records of the next staged footprint, loaded while the current view is computed:
+    // footprint row wave + 4 j is slot j of that wave, one column per lane (fw <= 64 and
+    // fh <= 4 kStageSlots for every staged footprint).
+    Rec pre[kStageSlots];
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    auto prefetch = [&](int k, uint2 f) {
+        const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
+        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
+        const auto vw = src.view(k);
+        const int cols = src.cols();
+        const int g = (rmin + wave) * cols + cmin + lane;  // record index in the staging view
+        if (lane < fw) {
+#pragma unroll
+            for (int j = 0; j < kStageSlots; ++j)
+                if (wave + 4 * j < fh) pre[j] = src.load(vw, g + 4 * j * cols);
+        }
+    };
+    auto staged = [](uint2 f) { return f.y != kFootprintSkip && f.y != kFootprintDirect; };
+    auto stage = [&](Rec* buf, uint2 f) {  // the prefetched records into LDS
+        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
+        if (lane < fw) {
+            Rec* dst = buf + wave * fw + lane;
+#pragma unroll
+            for (int j = 0; j < kStageSlots; ++j)
+                if (wave + 4 * j < fh) dst[4 * j * fw] = pre[j];
+        }
+    };
+    uint2 f_next = fp_row[0];
+    if (staged(f_next)) prefetch(0, f_next);
+
+    // One LDS buffer, two barriers per staged view.  (Two buffers and one barrier per view
+    // measured slower for 8-byte records: fewer blocks fit a CU.)
+    for (int k = 0; k < n_views; ++k) {
+        const uint2 f = f_next;  // the same for the whole block
+        if (staged(f)) {
+            __syncthreads();  // every wave is done with the previous footprint
+            stage(lds, f);
+            __syncthreads();
+        }
+        if (k + 1 < n_views) {
+            f_next = fp_row[k + 1];
+            if (staged(f_next)) prefetch(k + 1, f_next);
+        }
+        if (f.y == kFootprintSkip) continue;
+        const ViewConst& c = vc[k];
+        const auto view = src.view(k);
+        const float uxy = fmaf(c.p[1], Y, fmaf(c.p[0], X, c.p[3]));
+        const float vxy = fmaf(c.p[5], Y, fmaf(c.p[4], X, c.p[7]));
+        const float wxy = fmaf(c.p[9], Y, fmaf(c.p[8], X, c.p[11]));
+        if (f.y == kFootprintDirect) {
+            if (c.mode == kModeColumn) {
+                src.column(view, uxy, vxy, wxy, c.p[6], Z, acc);
+            } else if (c.mode == kModeSafe) {
+#pragma unroll
+                for (int i = 0; i < ZU; ++i)
+                    acc[i] += src.contrib_safe(view, fmaf(c.p[2], Z[i], uxy), fmaf(c.p[6], Z[i], vxy),
+                                               fmaf(c.p[10], Z[i], wxy));
+            } else {
+#pragma unroll
+                for (int i = 0; i < ZU; ++i)
+                    acc[i] += src.contrib_guarded(view, fmaf(c.p[2], Z[i], uxy), fmaf(c.p[6], Z[i], vxy),
+                                                  fmaf(c.p[10], Z[i], wxy));
+            }
+            continue;
+        }
+        const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
+        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
+        const float s_lo = (float)cmin, s_hi = (float)(cmin + fw - 1);
+        const float t_lo = (float)rmin, t_hi = (float)(rmin + fh - 1);
+        const int base = -(rmin * fw + cmin);
+        if (c.mode == kModeColumn) {
+            const float r = __builtin_amdgcn_rcpf(wxy);
+            const float sc = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), s_lo, s_hi);
+            const int c0 = (int)sc;
+            const float fx = __builtin_amdgcn_fractf(sc);
+            const float r2 = src.weight_column(view, r);
+            const float dt = c.p[6] * r;
+            const float tb = fmaf(vxy, r, 1.0f);
+            const int cb = base + c0;
+#pragma unroll
+            for (int i = 0; i < ZU; ++i) {
+                const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), t_lo, t_hi);
+                const int r0 = (int)t;
+                const float fy = __builtin_amdgcn_fractf(t);
+                acc[i] = fmaf(Src::eval(lds[__mul24(r0, fw) + cb], fx, fy), r2, acc[i]);
+            }
+        } else {  // safe
+#pragma unroll
+            for (int i = 0; i < ZU; ++i) {
+                const float u = fmaf(c.p[2], Z[i], uxy), v = fmaf(c.p[6], Z[i], vxy), w = fmaf(c.p[10], Z[i], wxy);
+                const float r = __builtin_amdgcn_rcpf(w);
+                const float sv = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), s_lo, s_hi);
+                const float tv = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), t_lo, t_hi);
+                const int c0 = (int)sv, r0 = (int)tv;
+                const float val = Src::eval(lds[__mul24(r0, fw) + c0 + base], __builtin_amdgcn_fractf(sv),
+                                            __builtin_amdgcn_fractf(tv));
+                acc[i] += val * src.weight_voxel(view, r);
+            }
+        }
+    }
+
+    if (in_xy) {
+        const size_t plane = (size_t)box.nx * (size_t)box.ny;
+        const size_t col = (size_t)y * box.nx + x;
+#pragma unroll
+        for (int i = 0; i < ZU; ++i) {
+            if (z0 + i < box.nz) {
+                float* p = vol + (size_t)(z0 + i) * plane + col;
+                *p += acc[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Footprints of a pass: for tile t and view k of the pass, the rectangle of
+// patch records [cmin, cmin + fw) x [rmin, rmin + fh) that the tile's voxels
+// can read.  The corners' positions (FP64, padded coordinates s = u/w + 1,
+// t = v/w + 1) bound every voxel's position (w > 0 on the box, so the image
+// of the tile is the convex hull of the corners' images); the rectangle adds
+// one record below and two above the corners' range on each axis, far more
+// than the FP32 rounding of the pass, and is cut to the bordered frame
+// [0, W+1] x [0, H+1].  Entry {0, kFootprintSkip}: the tile projects off the
+// detector (the test of cull_kernel, exact zeros); {0, kFootprintDirect}: a
+// guarded view, or a footprint wider than 64 records, taller than
+// kStageMaxHeight or of more than `cap` records.  One thread per (tile, view).
+// ---------------------------------------------------------------------------
+__global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
+                                 int gx, int gy, int n_tiles, int W, int H, int cap, uint2* __restrict__ out)
+{
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)n_tiles * n_views) return;
+    const int tile = (int)(id / n_views), k = (int)(id % n_views);
+    const ViewConst& c = vc[k];
+    if (c.mode == kModeGuarded) {
+        out[id] = make_uint2(0u, kFootprintDirect);
+        return;
+    }
+    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+    const int xs[2] = {bx * tx, min(bx * tx + tx - 1, box.nx - 1)};
+    const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
+    const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
+    bool left = true, right = true, top = true, bottom = true;
+    double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0;
+    for (int q = 0; q < 8; ++q) {
+        const double X = (double)box.ox + (double)box.vs * xs[q & 1];
+        const double Y = (double)box.oy + (double)box.vs * ys[(q >> 1) & 1];
+        const double Z = (double)box.oz + (double)box.vs * zs[q >> 2];
+        const double u = (double)c.p[0] * X + (double)c.p[1] * Y + (double)c.p[2] * Z + (double)c.p[3];
+        const double v = (double)c.p[4] * X + (double)c.p[5] * Y + (double)c.p[6] * Z + (double)c.p[7];
+        const double w = (double)c.p[8] * X + (double)c.p[9] * Y + (double)c.p[10] * Z + (double)c.p[11];
+        left &= u <= -2.0 * w;
+        right &= u >= (W + 1.0) * w;
+        top &= v <= -2.0 * w;
+        bottom &= v >= (H + 1.0) * w;
+        const double s = u / w + 1.0, t = v / w + 1.0;
+        smin = q ? fmin(smin, s) : s;
+        smax = q ? fmax(smax, s) : s;
+        tmin = q ? fmin(tmin, t) : t;
+        tmax = q ? fmax(tmax, t) : t;
+    }
+    if (left | right | top | bottom) {
+        out[id] = make_uint2(0u, kFootprintSkip);
+        return;
+    }
+    // fmin / fmax also map a NaN to the frame
+    const int c0 = (int)fmin(fmax(floor(smin) - 1.0, 0.0), (double)(W + 1));
+    const int c1 = (int)fmin(fmax(floor(smax) + 2.0, 0.0), (double)(W + 1));
+    const int r0 = (int)fmin(fmax(floor(tmin) - 1.0, 0.0), (double)(H + 1));
+    const int r1 = (int)fmin(fmax(floor(tmax) + 2.0, 0.0), (double)(H + 1));
+    const int fw = max(c1 - c0 + 1, 1), fh = max(r1 - r0 + 1, 1);
+    if (fw > kStageMaxWidth || fh > kStageMaxHeight || (long)fw * fh > cap) {
+        out[id] = make_uint2(0u, kFootprintDirect);
+        return;
+    }
+    out[id] = make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16), (uint32_t)fw | ((uint32_t)fh << 16));
+}
+
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Per-view constants: copy P_k and pick the view's branch.  w is affine, so
 // its extremes over the box are at the 8 corner voxels (evaluated in FP64).
 //   guarded  some voxel may have w < 1e-4 * max w (at or behind the source)
@@ -461,7 +726,11 @@ __global__ void prep_views_kernel(const float* __restrict__ mats, int n_views, B
         wmin = q ? fmin(wmin, w) : w;
         wmax = q ? fmax(wmax, w) : w;
     }
-    const bool safe = wmin > 0.0 && wmin >= 1e-4 * wmax;  // false for NaN
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) finite &= isfinite(c.p[i]);
+    // false for NaN; a non-finite matrix or a vanishing w also takes the guarded branch
+    const bool safe = finite && wmin > 0.0 && wmin >= 1e-4 * wmax && wmin > 1e-30;
     c.mode = !safe                                                  ? kModeGuarded
              : (column_ok && c.p[2] == 0.0f && c.p[10] == 0.0f) ? kModeColumn
                                                                 : kModeSafe;
@@ -637,6 +906,34 @@ hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, in
     return hipGetLastError();
 }
 
+template <class Src, int TX>
+hipError_t launch_zu_lds(int zu, float* vol, const Box& box, const ViewConst* vc, int n, const Src& src,
+                         const uint2* fp, int xcd_order, hipStream_t s)
+{
+    if (xcd_order >= 2) {
+        const int ax = xcd_order >> 1, ay = kXcds / ax;
+        const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + (kBlock / TX) - 1) / (kBlock / TX);
+        if (gx % ax != 0 || gy % ay != 0) xcd_order = 0;
+    }
+    const dim3 block(kBlock, 1, 1);
+    auto grid = [&](int z) {
+        const long t = n_tiles(box.nx, box.ny, box.nz, z, TX);
+        return dim3((unsigned)(xcd_order == 1 ? (t + kXcds - 1) / kXcds * kXcds : t));
+    };
+#define BP_LAUNCH(Z)                                                                                     \
+    hipLaunchKernelGGL((backproject_lds_kernel<Src, Z, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, fp, \
+                       xcd_order)
+    switch (zu) {
+    case 1: BP_LAUNCH(1); break;
+    case 2: BP_LAUNCH(2); break;
+    case 4: BP_LAUNCH(4); break;
+    case 8: BP_LAUNCH(8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef BP_LAUNCH
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, bool column_ok, ViewConst* out,
@@ -675,11 +972,24 @@ hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_u
     return hipGetLastError();
 }
 
+hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
+                            int cap, uint2* out, hipStream_t s)
+{
+    const int tx = tile_x, ty = kBlock / tile_x;
+    const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
+    const long tiles = n_tiles(box.nx, box.ny, box.nz, z_unroll, tile_x);
+    const long total = tiles * n;
+    const int threads = 256;
+    hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
+                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, cap, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void* out, uint32_t* maxabs,
                           float* inv_scale, hipStream_t s)
 {
-    hipError_t e = hipMemsetAsync(maxabs, 0, sizeof(uint32_t) * (size_t)n, s);
-    if (e != hipSuccess) return e;
+    // a fill kernel rather than a memset node, so that the call can be captured in a graph
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, maxabs, n);
     const dim3 rgrid(64, (unsigned)n), block(256, 1, 1);
     const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)(H + 2), (unsigned)n);
     f16x4_t* q = (f16x4_t*)out;
@@ -703,9 +1013,30 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 
 hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
-                              int xcd_order, const float* inv_scale, hipStream_t s)
+                              int xcd_order, const float* inv_scale, const uint2* fp, hipStream_t s)
 {
     const uint8_t* base = (const uint8_t*)src;
+    if (fp && layout == Layout::Patch16) {
+        const Patch16Source ps{base, W, H, inv_scale};
+        switch (tile_x) {
+        case 64: return launch_zu_lds<Patch16Source, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 32: return launch_zu_lds<Patch16Source, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 16: return launch_zu_lds<Patch16Source, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 8: return launch_zu_lds<Patch16Source, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (fp && layout == Layout::Patch) {
+        const PatchSource ps{base, W, H};
+        switch (tile_x) {
+        case 64: return launch_zu_lds<PatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 32: return launch_zu_lds<PatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 16: return launch_zu_lds<PatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 8: return launch_zu_lds<PatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (fp) return hipErrorInvalidValue;  // the plain path reads the caller's images
     if (layout == Layout::Patch16) {
         const Patch16Source ps{base, W, H, inv_scale};
         switch (tile_x) {

@@ -1,13 +1,17 @@
 """Serving loop: continuous batching of reconstruction requests on one GPU.
 
 Requests (volume edge L, number of views, storage dtype, phantom seed) arrive
-over time.  The server keeps a FIFO of arrived requests and admits the oldest
+over time.  A request's ingest makes its raw projections on the device (line
+integrals of its phantom, standing in for detector data) and runs the
+library's FDK pre-processing on them; then its volume is back projected.  The server keeps a FIFO of arrived requests and admits the oldest
 ones that fit -- in both the HBM budget (volume + projections + library
 scratch) and the in-flight limit -- whenever a slot and memory free up, not
 in fixed batches.  Every admitted request gets its own HIP stream and library
 context, so the back projections of different requests overlap on the device;
 a request whose inputs are still being made does not hold up the others.
-Latency is measured from arrival to the volume being ready.
+Latency is measured from arrival to the volume being ready; the device time
+of the ingest and of the back projection are recorded separately (HIP events
+on the request's stream).
 
 The executor does the device work; ``FakeExecutor`` stands in for it with
 simulated durations so the scheduling logic is testable on the CPU.
@@ -33,6 +37,8 @@ class Completed:
     updates: float
     footprint: int
     result: object = None
+    ingest_ms: float = None  # device time of the ingest (raw projections + FDK pre-processing)
+    bp_ms: float = None      # device time of the back projection
 
     @property
     def latency_s(self) -> float:
@@ -57,6 +63,15 @@ class Report:
     def summary(self) -> dict:
         lat = self.latencies()
         upd = sum(c.updates for c in self.completed)
+        timed = [c for c in self.completed if c.bp_ms is not None]
+        dev = {}
+        if timed:
+            ing = np.array([c.ingest_ms for c in timed])
+            bpm = np.array([c.bp_ms for c in timed])
+            dev = {"p50_ingest_ms": float(np.percentile(ing, 50)), "p99_ingest_ms": float(np.percentile(ing, 99)),
+                   "p50_backprojection_ms": float(np.percentile(bpm, 50)),
+                   "p99_backprojection_ms": float(np.percentile(bpm, 99)),
+                   "backprojection_gups": float(sum(c.updates for c in timed) / (bpm.sum() * 1e-3) / 1e9)}
         return {
             "requests": len(self.completed),
             "rejected": len(self.rejected),
@@ -67,6 +82,7 @@ class Report:
             "makespan_s": self.makespan_s,
             "peak_hbm_gib": self.peak_bytes / GIB,
             "peak_inflight": self.peak_inflight,
+            **dev,
         }
 
 
@@ -104,8 +120,9 @@ class Server:
             for rid in list(inflight):
                 h, r, fp, adm = inflight[rid]
                 if self.ex.poll(h):
-                    res = self.ex.finish(h)
-                    done.append(Completed(r.rid, r.arrival_s, adm, self.clock() - t0, self.ex.updates(r), fp, res))
+                    res, tm = self.ex.finish(h)
+                    done.append(Completed(r.rid, r.arrival_s, adm, self.clock() - t0, self.ex.updates(r), fp, res,
+                                          tm.get("ingest_ms"), tm.get("bp_ms")))
                     used -= fp
                     del inflight[rid]
                     progressed = True
@@ -169,12 +186,14 @@ class FakeExecutor:
         return self.clock() >= h[1]
 
     def finish(self, h):
-        return h[0].rid
+        return h[0].rid, {}
 
 
 class GpuExecutor:
-    """Per request: its own stream and context; inputs made on the device at admission, then
-    one back projection of all its views, accumulated into a zeroed volume.
+    """Per request: its own stream and context.  At admission its raw projections are made on
+    the device (line integrals, FP32) and weighted and filtered by the library's FDK
+    pre-processing into the request's storage dtype; then one back projection of all its
+    views is accumulated into a zeroed volume.
 
     keep_results: return each volume (on the host) from ``finish``; otherwise a checksum."""
 
@@ -197,6 +216,7 @@ class GpuExecutor:
         # call on it, so one context serves one in-flight request at a time; contexts are
         # kept for the executor's lifetime (destroying one synchronises the device).
         self._free_ctx = {}
+        self._fdk = {}  # FDK handles per detector geometry (safe to share between streams)
 
     def updates(self, r) -> float:
         return float(r.L) ** 3 * r.n_views
@@ -207,10 +227,11 @@ class GpuExecutor:
         vol = 4 * r.L ** 3
         proj = r.n_views * sc.W * sc.H * bpp
         k = min(r.n_views, self.tuning[0] or 32)
+        raw = r.n_views * sc.W * sc.H * 4 if self.fast_inputs else 0
         staging = k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
         cull = (r.L // 16) * (r.L // 16) * (r.L // 4 + 1) * ((r.n_views + 31) // 32) * 4
         gen = 6 * 62 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (62 views at a time)
-        return vol + proj + staging + cull + gen
+        return vol + proj + raw + staging + cull + gen
 
     def _matrices(self, sc):
         key = sc.geometry_args()[1:] + (sc.n_views, sc.arc_deg, sc.start_deg)
@@ -219,40 +240,63 @@ class GpuExecutor:
             self._mats[key] = self.torch.from_numpy(P32).to(self.dev)
         return self._mats[key]
 
+    def _fdk_for(self, sc):
+        key = (sc.W, sc.H, sc.pitch, sc.sid, sc.sdd)
+        if key not in self._fdk:
+            self._fdk[key] = self.bp.FdkFilter.for_scanner(sc, device=self.dev.index or 0)
+        return self._fdk[key]
+
     def start(self, r):
         torch = self.torch
         stream = torch.cuda.Stream(device=self.dev)  # default priority
         sc, v = self.scanner_fn(r), self.volume_fn(r)
         tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[r.dtype]
         mats = self._matrices(sc)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        raw = None
         with torch.cuda.stream(stream):
-            proj = synth.filtered_projections(sc, synth.random_ellipsoids(r.phantom_seed), device=self.dev,
-                                              out_dtype=tdt, chunk=62, fast=self.fast_inputs)
+            ev[0].record(stream)
+            ph = synth.random_ellipsoids(r.phantom_seed)
+            if self.fast_inputs:
+                # ingest: raw projections arrive (made here by the generator), the library filters them
+                raw = torch.empty((sc.n_views, sc.H, sc.W), dtype=torch.float32, device=self.dev)
+                for a in range(0, sc.n_views, 62):
+                    views = list(range(a, min(a + 62, sc.n_views)))
+                    raw[a:a + len(views)] = synth.line_integrals_fast(sc, ph, views, self.dev).to(torch.float32)
+                proj = self._fdk_for(sc).filter(raw, r.dtype, stream=stream)
+            else:
+                proj = synth.filtered_projections(sc, ph, device=self.dev, out_dtype=tdt, chunk=62)
             vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=self.dev)
+            ev[1].record(stream)
         key = (r.dtype, sc.W, sc.H)
         pool = self._free_ctx.setdefault(key, [])
         ctx = pool.pop() if pool else self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
         ctx.set_tuning("fused", *self.tuning)
         ctx.backproject(vol, proj, mats, v.voxel_size, v.origin, stream)
-        done = torch.cuda.Event()
-        done.record(stream)
-        return {"r": r, "stream": stream, "ctx": ctx, "key": key, "vol": vol, "proj": proj, "done": done}
+        ev[2].record(stream)
+        return {"r": r, "stream": stream, "ctx": ctx, "key": key, "vol": vol, "proj": proj, "raw": raw,
+                "done": ev[2], "ev": ev}
 
     def poll(self, h) -> bool:
         return h["done"].query()
 
     def finish(self, h):
         h["done"].synchronize()
+        ev = h["ev"]
+        tm = {"ingest_ms": ev[0].elapsed_time(ev[1]), "bp_ms": ev[1].elapsed_time(ev[2])}
         out = h["vol"].cpu().numpy() if self.keep else float(h["vol"].double().sum())
         self._free_ctx[h["key"]].append(h["ctx"])
         h.clear()
-        return out
+        return out, tm
 
     def close(self):
         for pool in self._free_ctx.values():
             for ctx in pool:
                 ctx.close()
         self._free_ctx.clear()
+        for f in self._fdk.values():
+            f.close()
+        self._fdk.clear()
 
 
 def main(argv=None):
@@ -275,22 +319,22 @@ def main(argv=None):
     args = ap.parse_args(argv)
     budget = int(args.budget_gib * GIB)
     base = synth.poisson_requests(args.requests, 1.0, args.seed)
-    phases = []
+    ex = GpuExecutor()
+    # warm-up (not reported): contexts, FDK handles, scratch and the allocator reach their
+    # largest sizes for every storage dtype of the mix
+    warm = [synth.Request(-1 - i, 0.0, 512, 496, dt, 99999 - i) for i, dt in enumerate(("f32", "f16"))]
+    Server(ex, budget, args.max_inflight).run(warm)
     if not args.rate:
         burst = [synth.Request(r.rid, 0.0, r.L, r.n_views, r.dtype, r.phantom_seed) for r in base]
-        ex = GpuExecutor()
         rep = Server(ex, budget, args.max_inflight).run(burst)
-        ex.close()
         cap = len(rep.completed) / rep.makespan_s
         s = rep.summary()
         s.update(phase="back_to_back", capacity_rps=cap)
         print(json.dumps(s), flush=True)
-        phases.append(s)
         rate = args.load * cap
     else:
         rate = args.rate
     stream = synth.poisson_requests(args.requests, rate, args.seed)
-    ex = GpuExecutor()
     rep = Server(ex, budget, args.max_inflight).run(stream)
     ex.close()
     s = rep.summary()

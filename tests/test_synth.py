@@ -72,3 +72,14 @@ def test_poisson_stream_is_seeded():
     assert [r.arrival_s for r in a] == [r.arrival_s for r in b]
     assert all(x.arrival_s <= y.arrival_s for x, y in zip(a, a[1:]))
     assert {r.L for r in a} <= {128, 256, 512}
+
+
+def test_generator_filter_agrees_with_the_fdk_oracle():
+    """The data recipe's FFT filter (FP64) and the oracle's FDK definition (Toeplitz product) agree."""
+    from oracle import fdk
+
+    sc = synth.Scanner(n_views=3, W=37, H=5, pitch=1.3, sid=600.0, sdd=950.0)
+    p = torch.from_numpy(np.random.default_rng(3).standard_normal((3, 5, 37)))
+    got = synth.fdk_filter(p, sc).numpy()
+    want = fdk.fdk_filter(p.numpy(), sc.pitch, sc.sid, sc.sdd)
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())

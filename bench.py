@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--no-cull", action="store_true", help="time without the clipping mask")
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
     ap.add_argument("--lds-taps", action="store_true", help="stage each tile's footprint through LDS")
+    ap.add_argument("--no-fdk", action="store_true", help="skip timing the FDK pre-processing of the stack")
     ap.add_argument("--cpu-block", type=int, default=160, help="edge of the centre block the oracle times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -171,6 +172,28 @@ def main():
     P = torch.from_numpy(P32).to(dev)
 
     updates = float(v.L) ** 3 * sc.n_views
+    # FDK pre-processing of a stack of this shape (the step before the path): the FP32 stack
+    # stands in for the raw projections (the filter's cost does not depend on the values)
+    fdk = None
+    if not args.no_fdk:
+        with bp.FdkFilter.for_scanner(sc) as f:
+            out = torch.empty_like(proj32)
+            for _ in range(2):
+                f.filter(proj32, "f32", out=out)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.steps):
+                f.filter(proj32, "f32", out=out)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / args.steps
+            del out
+        pix = float(sc.n_views) * sc.H * sc.W
+        fdk = {"kernel": "fdk_kernel", "ms_per_stack": round(ms, 3), "gpixel_per_s": round(pix / ms / 1e6, 2),
+               "hbm_gbs_algorithmic": round(pix * 8 / ms / 1e6, 1),
+               "hbm_frac": round(pix * 8 / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        log(f"bench: FDK pre-processing {fdk}")
     results = {}
     for form in forms:
         r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
@@ -257,6 +280,7 @@ def main():
         "forms": forms_out,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fdk_preprocessing": fdk,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

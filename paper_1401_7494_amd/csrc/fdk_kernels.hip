@@ -12,16 +12,18 @@
 // samples is zero-padded to N = 4096 >= 2W - 1, so the circular convolution of
 // length N equals the linear one on the W output samples.
 //
-// The length-4096 DFT runs as three radix-16 passes (4096 = 16^3), 16 points per
-// thread in registers, with the exchanges between passes through a padded LDS
-// buffer:
-//   n = 256 a + b,  k = k1 + 16 (c1 + 16 c2)
-//   pass 1 (thread b):         DFT16 over a, twiddle w4096^(b k1)
-//   pass 2 (thread (k1, d)):   DFT16 over c of element 16 c + d, twiddle w256^(d c1)
-//   pass 3 (thread k1 + 16 c1): DFT16 over d -> X[k1 + 16 c1 + 256 c2]
-// After pass 3 thread t holds X[t + 256 c2], c2 = 0..15, which is exactly the
-// input layout of pass 1 (thread b holds x[256 a + b]); so the inverse transform
-// starts in registers, and it leaves thread t with output sample t + 256 c2:
+// The length-4096 DFT runs as four radix-8 passes (4096 = 8^4), 8 points per
+// thread of a 512-thread workgroup, with the exchanges between passes through
+// an LDS buffer laid out so that every access of a wavefront spreads over all
+// banks:
+//   n = 512 a + b,  k = k1 + 8 (c1 + 8 (l1 + 8 l2))
+//   pass 1 (thread b):                 DFT8 over a, twiddle w4096^(b k1)
+//   pass 2 (thread (k1, d)):           DFT8 over c of element 64 c + d, twiddle w512^(d c1)
+//   pass 3 (thread (k1, c1, f)):       DFT8 over e of element 8 e + f, twiddle w64^(f l1)
+//   pass 4 (thread k1 + 8 c1 + 64 l1): DFT8 over f -> X[k1 + 8 c1 + 64 l1 + 512 l2]
+// After pass 4 thread t holds X[t + 512 l2], l2 = 0..7, which is exactly the
+// input layout of pass 1 (thread b holds x[512 a + b]); so the inverse transform
+// starts in registers, and it leaves thread t with output sample t + 512 l2:
 // coalesced loads and stores at both ends.
 #include <hip/hip_runtime.h>
 
@@ -35,19 +37,19 @@ namespace fdk {
 namespace {
 
 constexpr int kN = kTransform;
-constexpr int kThreads = 256;
-constexpr int kStride = 257;  // complex values per LDS row: consecutive k1 rows shift by 4 banks
+constexpr int kThreads = 512;
+constexpr int kIn = kN / 2 / kThreads;  // W <= N / 2: only elements 512 a + t with a < 4 can be inside a row
+// LDS layouts of the three exchanges (complex values)
+__device__ __forceinline__ int lds_y(int k1, int b) { return k1 * 512 + b; }
+__device__ __forceinline__ int lds_z(int k1, int c1, int d) { return k1 * 576 + c1 * 72 + d; }
+__device__ __forceinline__ int lds_q(int k1, int c1, int l1, int f) { return f * 513 + l1 * 64 + c1 * 8 + k1; }
+constexpr int kLds = 4600;  // largest index of the three layouts + 1
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
-}
-// a * conj(b)
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b)
-{
-    return make_double2(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y));
 }
 
 // In-place 4-point DFT; Dir = -1 forward (w4 = -i), +1 inverse (w4 = +i).
@@ -62,87 +64,88 @@ __device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, doub
     x3 = csub(b, jd);
 }
 
-// cos and sin of 2 pi m / 16 for m = 0..9
-__device__ __forceinline__ double2 w16(int m, int dir)
+// In-place 8-point DFT, natural order in and out: DFT4 of the even and of the odd
+// elements, then V[k] = E[k] + w8^k O[k] and V[k + 4] = E[k] - w8^k O[k].
+template <int Dir>
+__device__ __forceinline__ void dft8(double2 (&v)[8])
 {
-    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;  // pi/8
     constexpr double r2 = 0.70710678118654752440;
-    double c = 1.0, s = 0.0;
-    switch (m) {
-    case 1: c = c1; s = s1; break;
-    case 2: c = r2; s = r2; break;
-    case 3: c = s1; s = c1; break;
-    case 4: c = 0.0; s = 1.0; break;
-    case 6: c = -r2; s = r2; break;
-    case 9: c = -c1; s = -s1; break;
-    default: break;
-    }
-    return make_double2(c, dir * s);
+    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<Dir>(e0, e1, e2, e3);
+    dft4<Dir>(o0, o1, o2, o3);
+    // w8^1 = (r2, Dir r2), w8^2 = Dir i, w8^3 = (-r2, Dir r2)
+    const double2 t1 = make_double2(r2 * (o1.x - Dir * o1.y), r2 * (o1.y + Dir * o1.x));
+    const double2 t2 = Dir < 0 ? make_double2(o2.y, -o2.x) : make_double2(-o2.y, o2.x);
+    const double2 t3 = make_double2(-r2 * (o3.x + Dir * o3.y), r2 * (Dir * o3.x - o3.y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
 }
 
-// 16-point DFT of v[a], a = a0 + 4 a1.  Output V[k] lands in v[perm16(k)].
-__device__ __forceinline__ constexpr int perm16(int k) { return 4 * (k & 3) + (k >> 2); }
-
+// v[k] *= w^(m k) for k = 1..7, w = exp(Dir 2 pi i / N).  One entry of the table
+// tw[j] = exp(-2 pi i j / N) gives w^m and its powers are formed by products (at most
+// three roundings each, FP64): one table load per pass instead of seven, which halved
+// the kernel's time (the seven-load form streamed the 64 KB table through L2 per pass).
 template <int Dir>
-__device__ __forceinline__ void dft16(double2 (&v)[16])
+__device__ __forceinline__ void twiddle(double2 (&v)[8], const double2* __restrict__ tw, int m)
 {
-#pragma unroll
-    for (int a0 = 0; a0 < 4; ++a0) dft4<Dir>(v[a0], v[a0 + 4], v[a0 + 8], v[a0 + 12]);
-    // now v[a0 + 4 k1] = sum_a1 x[a0 + 4 a1] w4^(a1 k1); twiddle by w16^(a0 k1)
-#pragma unroll
-    for (int a0 = 1; a0 < 4; ++a0)
-#pragma unroll
-        for (int k1 = 1; k1 < 4; ++k1) v[a0 + 4 * k1] = cmul(v[a0 + 4 * k1], w16(a0 * k1, Dir));
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) dft4<Dir>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-    // v[4 k1 + k2] = V[k1 + 4 k2]
+    double2 p1 = tw[m];
+    if (Dir > 0) p1.y = -p1.y;
+    const double2 p2 = cmul(p1, p1), p3 = cmul(p2, p1), p4 = cmul(p2, p2);
+    v[1] = cmul(v[1], p1);
+    v[2] = cmul(v[2], p2);
+    v[3] = cmul(v[3], p3);
+    v[4] = cmul(v[4], p4);
+    v[5] = cmul(v[5], cmul(p4, p1));
+    v[6] = cmul(v[6], cmul(p3, p3));
+    v[7] = cmul(v[7], cmul(p4, p3));
 }
 
-// twiddle w^m (forward: exp(-2 pi i m / N), inverse: its conjugate)
+// One transform: v[a] holds element 512 a + t on entry; X[t + 512 l2] in v[l2] on return.
+// The caller separates uses of buf by a barrier.
 template <int Dir>
-__device__ __forceinline__ double2 twiddle(double2 v, const double2* __restrict__ tw, int m)
-{
-    const double2 w = tw[m];
-    return Dir < 0 ? cmul(v, w) : cmulc(v, w);
-}
-
-// Passes 2 and 3 and the exchanges before them; pass 1 output is in v (V[k1] at perm16(k1)),
-// already twiddled.  On return thread t holds X[t + 256 c2] at v[perm16(c2)].
-template <int Dir>
-__device__ __forceinline__ void passes_23(double2 (&v)[16], double2* buf, const double2* __restrict__ tw)
+__device__ __forceinline__ void fft4096(double2 (&v)[8], double2* buf, const double2* __restrict__ tw)
 {
     const int t = (int)threadIdx.x;
+    dft8<Dir>(v);  // pass 1: over a
+    twiddle<Dir>(v, tw, t);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) buf[k1 * kStride + t] = v[perm16(k1)];
+    for (int k1 = 0; k1 < 8; ++k1) buf[lds_y(k1, t)] = v[k1];
     __syncthreads();
     {
-        const int k1 = t >> 4, d = t & 15;
+        const int k1 = t >> 6, d = t & 63;  // pass 2: over c of element 64 c + d
 #pragma unroll
-        for (int c = 0; c < 16; ++c) v[c] = buf[k1 * kStride + 16 * c + d];
-        dft16<Dir>(v);
+        for (int c = 0; c < 8; ++c) v[c] = buf[lds_y(k1, 64 * c + d)];
+        dft8<Dir>(v);
+        twiddle<Dir>(v, tw, 8 * d);
+        __syncthreads();
 #pragma unroll
-        for (int c1 = 1; c1 < 16; ++c1) v[perm16(c1)] = twiddle<Dir>(v[perm16(c1)], tw, 16 * d * c1);
-        __syncthreads();  // every pass-2 read is done before the buffer is overwritten
-#pragma unroll
-        for (int c1 = 0; c1 < 16; ++c1) buf[k1 * kStride + 16 * c1 + d] = v[perm16(c1)];
+        for (int c1 = 0; c1 < 8; ++c1) buf[lds_z(k1, c1, d)] = v[c1];
     }
     __syncthreads();
     {
-        const int k1 = t & 15, c1 = t >> 4;
+        const int f = t & 7, c1 = (t >> 3) & 7, k1 = t >> 6;  // pass 3: over e of element 8 e + f
 #pragma unroll
-        for (int d = 0; d < 16; ++d) v[d] = buf[k1 * kStride + 16 * c1 + d];
-        dft16<Dir>(v);
+        for (int e = 0; e < 8; ++e) v[e] = buf[lds_z(k1, c1, 8 * e + f)];
+        dft8<Dir>(v);
+        twiddle<Dir>(v, tw, 64 * f);
+        __syncthreads();
+#pragma unroll
+        for (int l1 = 0; l1 < 8; ++l1) buf[lds_q(k1, c1, l1, f)] = v[l1];
     }
-}
-
-// Pass 1 on registers that hold x[256 a + t] in v[a]; output twiddled, V[k1] at v[perm16(k1)].
-template <int Dir>
-__device__ __forceinline__ void pass_1(double2 (&v)[16], const double2* __restrict__ tw)
-{
-    const int t = (int)threadIdx.x;
-    dft16<Dir>(v);
+    __syncthreads();
+    {
+        const int k1 = t & 7, c1 = (t >> 3) & 7, l1 = t >> 6;  // pass 4: over f
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) v[perm16(k1)] = twiddle<Dir>(v[perm16(k1)], tw, t * k1);
+        for (int f = 0; f < 8; ++f) v[f] = buf[lds_q(k1, c1, l1, f)];
+        dft8<Dir>(v);
+    }
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f)
@@ -172,12 +175,11 @@ __device__ __forceinline__ void store<uint16_t>(void* out, size_t idx, double x)
 
 // Rows r = view * H + j of the stack, two per workgroup (the last one alone if the count is odd).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fdk_kernel(const float* raw, void* out,
-                                                       long n_rows, int W, int H, Geometry g,
-                                                       const double2* __restrict__ tw,
+__global__ __launch_bounds__(kThreads) void fdk_kernel(const float* raw, void* out, long n_rows, int W, int H,
+                                                       Geometry g, const double2* __restrict__ tw,
                                                        const double* __restrict__ spectrum)
 {
-    __shared__ double2 buf[16 * kStride];
+    __shared__ double2 buf[kLds];
     const int t = (int)threadIdx.x;
     const long r0 = 2 * (long)blockIdx.x;
     const bool two = r0 + 1 < n_rows;
@@ -187,44 +189,34 @@ __global__ __launch_bounds__(kThreads) void fdk_kernel(const float* raw, void* o
     const double vb = ((double)(int)((r0 + 1) % H) - g.half_h) * g.pitch;
     const double sa = fma(va, va, g.sdd2), sb = fma(vb, vb, g.sdd2);
 
-    double2 v[16];
+    double2 v[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = make_double2(0.0, 0.0);
+    for (int i = 0; i < 8; ++i) v[i] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int i = 0; i < kN / 2 / kThreads; ++i) {  // W <= N / 2: only a < 8 can be inside the row
+    for (int i = 0; i < kIn; ++i) {
         const int n = kThreads * i + t;
         if (n < W) {
             const double u = ((double)n - g.half_w) * g.pitch;
-            const double ca = g.sdd / sqrt(fma(u, u, sa));
-            const double cb = g.sdd / sqrt(fma(u, u, sb));
-            v[i].x = (double)a[n] * ca;
-            if (two) v[i].y = (double)b[n] * cb;
+            v[i].x = (double)a[n] * (g.sdd / sqrt(fma(u, u, sa)));
+            if (two) v[i].y = (double)b[n] * (g.sdd / sqrt(fma(u, u, sb)));
         }
     }
-    // forward transform
-    pass_1<-1>(v, tw);
-    passes_23<-1>(v, buf, tw);
-    // thread t holds X[t + 256 c2]: apply the ramp (with tau and 1 / N folded in)
+    fft4096<-1>(v, buf, tw);
+    // thread t holds X[t + 512 l2]: apply the ramp (with tau and 1 / N folded in)
 #pragma unroll
-    for (int c2 = 0; c2 < 16; ++c2) {
-        const double s = spectrum[t + kThreads * c2];
-        v[perm16(c2)].x *= s;
-        v[perm16(c2)].y *= s;
+    for (int l2 = 0; l2 < 8; ++l2) {
+        const double s = spectrum[t + kThreads * l2];
+        v[l2].x *= s;
+        v[l2].y *= s;
     }
-    // inverse transform: v[a] must hold element 256 a + t
-    double2 x[16];
+    __syncthreads();  // the forward pass-4 reads are done before the buffer is reused
+    fft4096<1>(v, buf, tw);  // v[a] holds element 512 a + t, as pass 1 wants
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = v[perm16(i)];
-    pass_1<1>(x, tw);
-    __syncthreads();  // the forward pass-3 reads are done before the buffer is reused
-    passes_23<1>(x, buf, tw);
-#pragma unroll
-    for (int c2 = 0; c2 < kN / 2 / kThreads; ++c2) {
-        const int n = t + kThreads * c2;
+    for (int l2 = 0; l2 < kIn; ++l2) {
+        const int n = t + kThreads * l2;
         if (n < W) {
-            const double2 y = x[perm16(c2)];
-            store<T>(out, (size_t)r0 * W + n, y.x);
-            if (two) store<T>(out, (size_t)(r0 + 1) * W + n, y.y);
+            store<T>(out, (size_t)r0 * W + n, v[l2].x);
+            if (two) store<T>(out, (size_t)(r0 + 1) * W + n, v[l2].y);
         }
     }
 }

@@ -13,6 +13,8 @@ Forms timed on the same GPU and inputs:
   plain_f32    one volume pass per view (the paper's one-call-per-projection form)
   fused_bf16   fused, projections stored as BF16 (FP32 interpolation and accumulation)
   fused_f16    fused, projections stored as FP16
+  direct_f32   fused, taps from the caller's images (no staging copy; small volumes)
+  auto_f32     the library's own choice of path
 
 Prints one JSON line.  Each form's error is stated against the FP64 oracle on
 the FP32 data over the centre 128^3 block (the CPU-baseline sample).
@@ -95,7 +97,8 @@ def log(msg):
 
 def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
               no_column=False, order="region", region_ax=0, lds_taps=False):
-    path, dt = form.split("_")
+    path, dt = form.rsplit("_", 1)
+    path = {"direct": "fused_direct"}.get(path, path)
     proj = proj_by_dtype[dt]
     n, H, W = proj.shape
     L = vol_cfg.L

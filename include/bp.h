@@ -69,9 +69,15 @@ typedef enum {
     BP_PATH_AUTO = 0,   /* the tuned choice for (dtype, volume size) */
     BP_PATH_PLAIN = 1,  /* one volume pass per view, taps read from the caller's images
                            with the per-tap detector bounds of Listing 1 (Sec. 4.1) */
-    BP_PATH_FUSED = 2   /* views_per_pass views per volume pass, accumulated in
+    BP_PATH_FUSED = 2,  /* views_per_pass views per volume pass, accumulated in
                            registers; taps read from a zero-padded staging copy
                            (Sec. 5.1.1), so no per-tap bounds tests */
+    BP_PATH_FUSED_DIRECT = 3 /* views_per_pass views per volume pass, taps read from
+                           the caller's images with per-tap bounds (no staging copy):
+                           for volumes small next to the projections, where writing
+                           the staging copy would cost more than the taps save.
+                           BP_PATH_AUTO takes it when the box has fewer than 8 x W x H
+                           voxels */
 } bp_path;
 
 typedef struct {

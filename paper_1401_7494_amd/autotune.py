@@ -53,12 +53,15 @@ class Result:
 
 
 def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, txs=TX_CANDIDATES, include_plain=True):
-    """Plain passes (64-wide tiles) and fused passes over K x ZU x tile width."""
+    """Plain passes (64-wide tiles), fused passes over K x ZU x tile width, and fused passes on the
+    caller's images (16- and 64-wide tiles)."""
     zus = [zu for zu in zus if zu <= max(problem.nz, 1)]
     out = []
     if include_plain:
         out += [Candidate("plain", 1, zu, 64) for zu in zus]
     out += [Candidate("fused", k, zu, tx) for k in ks if k <= problem.n_views for zu in zus for tx in txs]
+    out += [Candidate("fused_direct", k, zu, tx) for k in ks if k <= problem.n_views for zu in zus
+            for tx in txs if tx in (16, 64)]
     return out
 
 

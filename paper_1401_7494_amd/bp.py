@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbp.so")
 
 BP_OK, BP_ERR_INVALID_ARG, BP_ERR_UNSUPPORTED, BP_ERR_OUT_OF_MEMORY, BP_ERR_DEVICE, BP_ERR_LAUNCH = range(6)
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
-PATHS = {"auto": 0, "plain": 1, "fused": 2}
+PATHS = {"auto": 0, "plain": 1, "fused": 2, "fused_direct": 3}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 
 # Every function the header declares, with its ctypes signature.

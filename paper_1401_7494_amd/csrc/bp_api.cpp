@@ -161,9 +161,19 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
 {
     Plan p;
     p.path = ctx->path_override != BP_PATH_AUTO ? ctx->path_override : ctx->cfg.path;
-    if (p.path == BP_PATH_AUTO) p.path = BP_PATH_FUSED;
+    if (p.path == BP_PATH_AUTO) {
+        // the staging copy writes 16 (8) bytes per pixel of every view: for a small box that
+        // costs more than the taps it saves (measured crossover between L = 128 and 256 at
+        // 1248 x 960 pixels)
+        const double voxels = (double)nx * (double)ny * (double)nz;
+        p.path = voxels < 8.0 * ctx->cfg.det_width * (double)ctx->cfg.det_height ? BP_PATH_FUSED_DIRECT
+                                                                                  : BP_PATH_FUSED;
+    }
     p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
-    if (p.k <= 0) p.k = ctx->cfg.proj_dtype == BP_F32 ? 32 : 64;  // 8-byte staging records halve the pass footprint
+    if (p.k <= 0) {
+        if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
+        else p.k = ctx->cfg.proj_dtype == BP_F32 ? 32 : 64;  // 8-byte staging records halve the pass footprint
+    }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;
     p.zu = ctx->zu_override > 0 ? ctx->zu_override : ctx->cfg.z_unroll;
@@ -171,8 +181,8 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     while (p.zu > 1 && p.zu > nz) p.zu >>= 1;
     p.tx = ctx->tx_override > 0 ? ctx->tx_override : ctx->cfg.tile_x;
     if (p.tx <= 0) p.tx = 16;
-    // the plain path comes in 16- and 64-wide tiles, the pair layout in 64-wide tiles
-    if (p.path == BP_PATH_PLAIN && p.tx != 16) p.tx = 64;
+    // the caller's-image taps come in 16- and 64-wide tiles
+    if ((p.path == BP_PATH_PLAIN || p.path == BP_PATH_FUSED_DIRECT) && p.tx != 16) p.tx = 64;
 
     (void)nx;
     (void)ny;
@@ -229,7 +239,8 @@ bp_status bp_create(const bp_config* cfg, bp_ctx* out)
         return BP_ERR_UNSUPPORTED;  // one view must fit a 32-bit buffer offset
     if (cfg->proj_dtype != BP_F32 && cfg->proj_dtype != BP_F16 && cfg->proj_dtype != BP_BF16)
         return BP_ERR_INVALID_ARG;
-    if (cfg->path != BP_PATH_AUTO && cfg->path != BP_PATH_PLAIN && cfg->path != BP_PATH_FUSED)
+    if (cfg->path != BP_PATH_AUTO && cfg->path != BP_PATH_PLAIN && cfg->path != BP_PATH_FUSED &&
+        cfg->path != BP_PATH_FUSED_DIRECT)
         return BP_ERR_INVALID_ARG;
     if (cfg->views_per_pass < 0 || (cfg->z_unroll != 0 && !valid_zu(cfg->z_unroll)) ||
         (cfg->tile_x != 0 && !valid_tx(cfg->tile_x)))
@@ -272,7 +283,7 @@ bp_status bp_destroy(bp_ctx ctx)
 bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll, int tile_x)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
-    if (path != BP_PATH_AUTO && path != BP_PATH_PLAIN && path != BP_PATH_FUSED)
+    if (path != BP_PATH_AUTO && path != BP_PATH_PLAIN && path != BP_PATH_FUSED && path != BP_PATH_FUSED_DIRECT)
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown path");
     if (views_per_pass < 0) return fail(ctx, BP_ERR_INVALID_ARG, "views_per_pass < 0");
     if (z_unroll != 0 && !valid_zu(z_unroll)) return fail(ctx, BP_ERR_INVALID_ARG, "z_unroll not in {1,2,4,8}");
@@ -368,7 +379,8 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
     const bool lds = layout != bp::Layout::Checked && (ctx->options & BP_OPT_LDS_TAPS) && W + 2 < 65536 &&
                      H + 2 < 65536;
-    const bool culled = layout != bp::Layout::Checked && !lds && !(ctx->options & BP_OPT_NO_CULL);
+    const bool culled = (layout != bp::Layout::Checked || plan.path == BP_PATH_FUSED_DIRECT) && !lds &&
+                        !(ctx->options & BP_OPT_NO_CULL);
     const long tiles = bp::n_tiles(nx, ny, nz, plan.zu, plan.tx);
     const int words = bp::cull_words(n_views);
 

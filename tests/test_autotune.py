@@ -11,6 +11,7 @@ def test_candidates_cover_the_required_views_per_pass():
     assert {c.z_unroll for c in cands} == {1, 2, 4, 8}
     assert {c.tile_x for c in cands if c.path == "fused"} == {8, 16, 32, 64}
     assert all(c.tile_x == 64 for c in cands if c.path == "plain")
+    assert {c.tile_x for c in cands if c.path == "fused_direct"} == {16, 64}
     small = at.candidates(at.Problem(64, 64, 2, 3, "f32", 64, 64))
     assert all(c.z_unroll <= 2 and c.views_per_pass <= 3 for c in small)
 

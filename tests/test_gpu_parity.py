@@ -48,7 +48,7 @@ def small_inputs():
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("path,k,tx", [("plain", 1, 64), ("plain", 1, 16), ("fused", 4, 16), ("fused", 13, 8),
-                                       ("fused", 32, 64)])
+                                       ("fused", 32, 64), ("fused_direct", 5, 16), ("fused_direct", 13, 64)])
 @pytest.mark.parametrize("zu", [1, 2, 4, 8])
 def test_parity_small_ragged(small_inputs, dtype, path, k, tx, zu):
     proj32, P32 = small_inputs
@@ -197,7 +197,7 @@ def test_allocation_failure_is_reported(monkeypatch, small_inputs):
 def test_plan_reports_choices():
     with bp.Context(1248, 960, "f32") as ctx:
         p = ctx.plan(512, 512, 512, 496)
-        assert p.path in ("plain", "fused") and p.z_unroll in (1, 2, 4, 8)
+        assert p.path == "fused" and p.z_unroll in (1, 2, 4, 8)
         ctx.set_tuning("plain", 0, 4, 16)
         p = ctx.plan(512, 512, 512, 496)
         assert (p.path, p.views_per_pass, p.z_unroll, p.tile_x) == ("plain", 1, 4, 16)
@@ -206,6 +206,12 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused", 500, 2, 8)
         p = ctx.plan(64, 64, 64, 496)
         assert (p.views_per_pass, p.tile_x) == (496, 8)
+        ctx.set_tuning("auto", 0, 0, 0)  # small boxes read the caller's images, large ones the staging copy
+        assert ctx.plan(128, 128, 128, 496).path == "fused_direct"
+        assert ctx.plan(256, 256, 256, 496).path == "fused"
+        ctx.set_tuning("fused_direct", 0, 0, 32)
+        p = ctx.plan(128, 128, 128, 496)
+        assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
 
 
 # ---------------------------------------------------------------------------

@@ -271,7 +271,7 @@ class GpuExecutor:
         key = (r.dtype, sc.W, sc.H)
         pool = self._free_ctx.setdefault(key, [])
         ctx = pool.pop() if pool else self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
-        ctx.set_tuning("fused", *self.tuning)
+        ctx.set_tuning("auto", *self.tuning)
         ctx.backproject(vol, proj, mats, v.voxel_size, v.origin, stream)
         ev[2].record(stream)
         return {"r": r, "stream": stream, "ctx": ctx, "key": key, "vol": vol, "proj": proj, "raw": raw,

@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
     ap.add_argument("--lds-taps", action="store_true", help="stage each tile's footprint through LDS")
     ap.add_argument("--no-fdk", action="store_true", help="skip timing the FDK pre-processing of the stack")
-    ap.add_argument("--cpu-block", type=int, default=160, help="edge of the centre block the oracle times")
+    ap.add_argument("--cpu-block", type=int, default=320,
+                    help="edge of the centre block the oracle times (about 10 s of FP64 work on 16 threads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     return ap.parse_args()

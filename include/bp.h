@@ -146,10 +146,14 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     compact FP16 coefficients (8 bytes, scaled per view by a
  *                     power of two; adds the rounding of the pixel differences
  *                     to FP16, ~2^-11 relative)
- *   BP_OPT_LDS_TAPS   fused path: for every (block tile, view) copy the tile's
- *                     footprint of the staging buffer into LDS with coalesced row
- *                     loads and read the taps from there (results bit-identical;
- *                     the clipping mask is then part of the footprint table)
+ *   BP_OPT_DIRECT_TAPS  fused path: read every tap directly through the vector
+ *                     L1 cache.  By default the fused path copies, for every
+ *                     (block tile, view), the tile's footprint of the staging
+ *                     buffer into LDS with coalesced row loads and reads the
+ *                     taps from there, for all views but a share of them
+ *                     (bp_set_tap_split) that still read directly, so that the
+ *                     pass draws on both paths at once.  Results are
+ *                     bit-identical either way.
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of
@@ -167,8 +171,14 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_XCD_REGION_SHIFT 5
 #define BP_OPT_XCD_REGION_MASK (15 << BP_OPT_XCD_REGION_SHIFT)
 #define BP_OPT_XCD_REGION(ax) ((ax) << BP_OPT_XCD_REGION_SHIFT)
-#define BP_OPT_LDS_TAPS (1 << 9)
+#define BP_OPT_DIRECT_TAPS (1 << 9)
 bp_status bp_set_options(bp_ctx ctx, int options);
+
+/* Fused path with LDS staging: of every 8 consecutive views of a pass, how many
+ * read their taps directly through L1 instead of from the LDS stage (0..8);
+ * -1 restores the tuned share (4 for FP32 staging records, 3 for compact ones).
+ * Results are bit-identical for every share. */
+bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,

@@ -59,6 +59,7 @@ SIGNATURES = {
                                     ctypes.POINTER(_c_float), _vp]),
     "bp_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
     "bp_set_options": (_c_int, [_vp, _c_int]),
+    "bp_set_tap_split": (_c_int, [_vp, _c_int]),
     "bp_query_plan": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
     "bp_circular_matrices": (_c_int, [_vp, _c_int, _c_double, _c_double, _c_double, _c_int, _c_int, _vp, _vp]),
@@ -184,14 +185,15 @@ class Context:
     OPT_WIDE_STAGING = 8
     OPT_PLAIN_ORDER = 16
     OPT_XCD_REGION_SHIFT = 5
-    OPT_LDS_TAPS = 1 << 9
+    OPT_DIRECT_TAPS = 1 << 9
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
-                    order: str = "region", region_ax: int = 0, lds_taps: bool = False):
+                    order: str = "region", region_ax: int = 0, direct_taps: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
         projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
-        each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices")."""
+        each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices"); read every tap
+        of the fused path directly instead of staging most views' footprints through LDS."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
                  | (self.OPT_WIDE_STAGING if wide_staging else 0))
         if order == "plain":
@@ -201,9 +203,13 @@ class Context:
         elif order != "region":
             raise ValueError(f"order must be one of {self.ORDERS}")
         flags |= int(region_ax) << self.OPT_XCD_REGION_SHIFT
-        if lds_taps:
-            flags |= self.OPT_LDS_TAPS
+        if direct_taps:
+            flags |= self.OPT_DIRECT_TAPS
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
+
+    def set_tap_split(self, direct_eighths: int = -1):
+        """Of every 8 views of a staged pass, how many read their taps directly (-1 = tuned)."""
+        self._check(lib().bp_set_tap_split(self._h, int(direct_eighths)), "bp_set_tap_split")
 
     KERNELS = {"backproject": 0, "pad": 1, "views": 2}
 

@@ -35,6 +35,7 @@ struct bp_ctx_s {
     int k_override = 0;
     int zu_override = 0;
     int tx_override = 0;
+    int tap_split = -1;  // views of every 8 of a staged pass that read directly; -1 = tuned
     // kernel timing (bp_enable_timing): event pairs per kernel kind
     bool timing = false;
     struct Pair {
@@ -148,6 +149,13 @@ bp_status drain_timing(bp_ctx ctx)
     return st;
 }
 
+// Does the fused path stage its taps through LDS?  (The footprint table packs padded rows
+// and columns into 16 bits.)
+bool staged_taps(const bp_ctx_s* ctx, bp::Layout layout, int W, int H)
+{
+    return layout != bp::Layout::Checked && !(ctx->options & BP_OPT_DIRECT_TAPS) && W + 2 < 65536 && H + 2 < 65536;
+}
+
 struct Plan {
     bp_path path;
     int k;
@@ -171,8 +179,10 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     }
     p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
     if (p.k <= 0) {
+        const bool compact = ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING);
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
-        else p.k = ctx->cfg.proj_dtype == BP_F32 ? 32 : 64;  // 8-byte staging records halve the pass footprint
+        else if (ctx->options & BP_OPT_DIRECT_TAPS) p.k = compact ? 64 : 32;  // 8-byte records halve the footprint
+        else p.k = compact ? 128 : 64;  // LDS-staged taps (measured at L = 512, 496 views)
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;
@@ -295,6 +305,14 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
     return BP_OK;
 }
 
+bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (direct_eighths < -1 || direct_eighths > 8) return fail(ctx, BP_ERR_INVALID_ARG, "tap split not in -1..8");
+    ctx->tap_split = direct_eighths;
+    return BP_OK;
+}
+
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path* path, int* views_per_pass,
                         int* z_unroll, int* tile_x)
 {
@@ -311,7 +329,7 @@ bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
-                    BP_OPT_XCD_REGION_MASK | BP_OPT_LDS_TAPS))
+                    BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
     if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
@@ -377,11 +395,12 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
         layout = bp::Layout::Patch16;
     // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
-    const bool lds = layout != bp::Layout::Checked && (ctx->options & BP_OPT_LDS_TAPS) && W + 2 < 65536 &&
-                     H + 2 < 65536;
+    const bool lds = staged_taps(ctx, layout, W, H);
     const bool culled = (layout != bp::Layout::Checked || plan.path == BP_PATH_FUSED_DIRECT) && !lds &&
                         !(ctx->options & BP_OPT_NO_CULL);
     const long tiles = bp::n_tiles(nx, ny, nz, plan.zu, plan.tx);
+    // share of the views of each 8 that read directly while the others are staged (tuned at L = 512)
+    const int split = ctx->tap_split >= 0 ? ctx->tap_split : (layout == bp::Layout::Patch ? 4 : 3);
     const int words = bp::cull_words(n_views);
 
     // all scratch first: a call that fails here has enqueued nothing
@@ -446,7 +465,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             if (lds) {
                 e = timed(ctx, 2, s, [&] {
                     return bp::launch_footprint(ctx->d_views + k0, kc, box, plan.zu, plan.tx, W, H,
-                                                bp::kStageRecords, fp, s);
+                                                bp::kStageRecords, split, fp, s);
                 });
                 if (e != hipSuccess)
                     return fail(ctx, BP_ERR_LAUNCH, std::string("footprint kernel: ") + hipGetErrorString(e));

@@ -86,9 +86,10 @@ constexpr int kStageRecords = 2048;
 constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
 
 
-// Footprint table of one pass: n views (view constants vc[0, n)), every tile.
+// Footprint table of one pass: n views (view constants vc[0, n)), every tile;
+// views with k % 8 < direct_eighths are marked to read their taps directly.
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            int cap, uint2* out, hipStream_t s);
+                            int cap, int direct_eighths, uint2* out, hipStream_t s);
 
 // Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
 inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)

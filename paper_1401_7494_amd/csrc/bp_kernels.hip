@@ -638,11 +638,15 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // than the FP32 rounding of the pass, and is cut to the bordered frame
 // [0, W+1] x [0, H+1].  Entry {0, kFootprintSkip}: the tile projects off the
 // detector (the test of cull_kernel, exact zeros); {0, kFootprintDirect}: a
-// guarded view, or a footprint wider than 64 records, taller than
-// kStageMaxHeight or of more than `cap` records.  One thread per (tile, view).
+// guarded view, a footprint wider than 64 records, taller than
+// kStageMaxHeight or of more than `cap` records, or one of the views k with
+// k % 8 < direct_eighths -- those read their taps directly, so that the
+// pass draws on the L1 path and the LDS path at once.  One thread per
+// (tile, view).
 // ---------------------------------------------------------------------------
 __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
-                                 int gx, int gy, int n_tiles, int W, int H, int cap, uint2* __restrict__ out)
+                                 int gx, int gy, int n_tiles, int W, int H, int cap, int direct_eighths,
+                                 uint2* __restrict__ out)
 {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long)n_tiles * n_views) return;
@@ -677,6 +681,10 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     }
     if (left | right | top | bottom) {
         out[id] = make_uint2(0u, kFootprintSkip);
+        return;
+    }
+    if ((k & 7) < direct_eighths) {  // this share of the views reads its taps directly (through L1)
+        out[id] = make_uint2(0u, kFootprintDirect);
         return;
     }
     // fmin / fmax also map a NaN to the frame
@@ -973,7 +981,7 @@ hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_u
 }
 
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            int cap, uint2* out, hipStream_t s)
+                            int cap, int direct_eighths, uint2* out, hipStream_t s)
 {
     const int tx = tile_x, ty = kBlock / tile_x;
     const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
@@ -981,7 +989,7 @@ hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_un
     const long total = tiles * n;
     const int threads = 256;
     hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
-                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, cap, out);
+                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, cap, direct_eighths, out);
     return hipGetLastError();
 }
 

@@ -280,7 +280,7 @@ def test_parity_l512_sampled(dtype, compact):
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              order="region", region_ax=0, lds_taps=False, wide_staging=False):
+              order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -289,7 +289,8 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
-                        lds_taps=lds_taps, wide_staging=wide_staging)
+                        direct_taps=direct_taps, wide_staging=wide_staging)
+        ctx.set_tap_split(tap_split)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
@@ -340,8 +341,11 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
         assert np.array_equal(a, b), (order, ax)
     c = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, no_cull=True)
     assert np.array_equal(a, c)
-    d = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, lds_taps=True)
-    assert np.array_equal(a, d), "LDS-staged taps"
+    d = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, direct_taps=True)
+    assert np.array_equal(a, d), "direct taps"
+    for split in (0, 8):
+        e = _run_opts(proj32, P32, BOX, VS, origin, k=5, zu=zu, tx=tx, tap_split=split)
+        assert np.array_equal(a, e), ("tap split", split)
     # a box whose tile grid divides into XCD regions takes the region order itself
     shape8 = (9, 8 * (256 // tx), 8 * tx)
     o8 = _box_origin(shape8, VS)
@@ -355,9 +359,9 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
 
 @pytest.mark.parametrize("dtype,wide", [("f32", False), ("f16", False), ("bf16", False), ("bf16", True)])
 def test_lds_staged_taps_are_bit_identical(dtype, wide):
-    """Taps staged through LDS per (tile, view) footprint give the same bits as direct taps: column
-    and general branches, culled tiles, guarded views (direct inside the staged pass), and
-    footprints too large for LDS (direct as well)."""
+    """Taps staged through LDS per (tile, view) footprint give the same bits as direct taps, for any
+    share of views read directly: column and general branches, culled tiles, guarded views (direct
+    inside the staged pass), and footprints too large for LDS (direct as well)."""
     sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)
     proj = synth.filtered_projections(sc, synth.random_ellipsoids(77))
     if dtype != "f32":
@@ -369,10 +373,12 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
     for shape, vs, kw in cases:
         origin = _box_origin(shape, vs)
         for tx, zu in ((16, 8), (64, 1), (8, 4)):
-            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide, **kw)
-            b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
-                          lds_taps=True, **kw)
-            assert np.array_equal(a, b), (shape, vs, kw, tx, zu)
+            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
+                          direct_taps=True, **kw)
+            for split in (-1, 0, 5):  # tuned share of direct views, all staged, 5 of 8 direct
+                b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
+                              tap_split=split, **kw)
+                assert np.array_equal(a, b), (shape, vs, kw, tx, zu, split)
             assert np.abs(a).max() > 0
 
 
@@ -429,17 +435,18 @@ def test_parity_l1024_sampled():
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_lds_staged_taps_bit_identical_at_l512(dtype):
-    """At the benchmark size (512^3, 496 views of 1248 x 960, default tuning) the LDS-staged taps
-    reproduce the direct pass bit for bit over the whole volume."""
+    """At the benchmark size (512^3, 496 views of 1248 x 960, K = 64) the LDS-staged taps (with the
+    tuned share of direct views) reproduce the direct pass bit for bit over the whole volume."""
     wl = synth.WORKLOADS["fdk_l512_v496_f32"]
     v = wl.volume
     proj = gc.full_projections(wl.phantom_seed, dtype)
     P = torch.from_numpy(gc.product_matrices(wl.scanner)).to("cuda:0")
     out = []
-    for lds in (False, True):
+    for direct in (True, False):
         vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device="cuda:0")
         with bp.Context(wl.scanner.W, wl.scanner.H, dtype) as ctx:
-            ctx.set_options(lds_taps=lds)
+            ctx.set_tuning("fused", 64, 0, 0)  # the same views per pass: the same summation order
+            ctx.set_options(direct_taps=direct)
             ctx.backproject(vol, proj, P, v.voxel_size, v.origin)
             torch.cuda.synchronize()
         out.append(vol)

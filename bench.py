@@ -52,10 +52,10 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel: str, launch: str, workload: str):
     """HBM-side bytes per launch of the fused FP32 pass from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a copy of known size), or None when the kernel sources
-    have changed since the counters were taken."""
+    have changed since the counters were taken or the summary is for another kernel or launch."""
     path = os.path.join(ROOT, COUNTERS_MD)
     if not os.path.exists(path):
         return None
@@ -63,7 +63,9 @@ def measured_traffic():
     if "```json" not in text:
         return None
     rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    if rec.get("kernel_source_sha256") != kernel_source_sha():
+    if rec.get("kernel_source_sha256") != kernel_source_sha() or rec.get("kernel") != kernel:
+        return None
+    if rec.get("launch_key") != launch or rec.get("workload") != workload:
         return None
     return (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"]) * 1024
 
@@ -245,11 +247,13 @@ def main():
     per_launch_ms = ms_bp / max(n_bp, 1)
     updates_per_launch = updates * args.steps / max(n_bp, 1)
     achieved = updates_per_launch * VALU_PER_UPDATE / (per_launch_ms * 1e-3) / 1e12
-    traffic = measured_traffic() if head is results.get("fused_f32") else None
+    kernel = "backproject_kernel" if args.direct_taps else "backproject_lds_kernel"
+    launch = f"K={head['views_per_pass']} ZU={head['z_unroll']} TX={head['tile_x']} split={args.tap_split}"
+    traffic = measured_traffic(kernel, launch, wl.name) if head is results.get("fused_f32") else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_T, 3),
                 "unit": "Tinstr/s", "frac": round(achieved / VALU_PEAK_T, 4),
                 "traffic": round(traffic) if traffic else None,
-                "kernel": "backproject_kernel", "avg_launch_ms": round(per_launch_ms, 4),
+                "kernel": kernel, "avg_launch_ms": round(per_launch_ms, 4),
                 "updates_per_launch": updates_per_launch, "valu_instr_per_update": VALU_PER_UPDATE}
 
     forms_out = {}

@@ -136,7 +136,7 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
     out = vol / float(steps)  # every step added the same reconstruction
     return {
         "path": plan.path, "dtype": dt, "views_per_pass": plan.views_per_pass, "z_unroll": plan.z_unroll,
-        "tile_x": plan.tile_x,
+        "tile_x": plan.tile_x, "direct_taps": plan.direct_taps,
         "step_ms": step_ms, "wall_s": wall, "kernels": kern, "volume": out,
     }
 
@@ -211,7 +211,8 @@ def main():
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9
         r["gups_p99"] = updates / (np.percentile(ms, 99) * 1e-3) / 1e9
         log(f"bench: {form}: {ms.mean():.2f} ms/step  p50 {r['gups_p50']:.1f} GUPS  p99 {r['gups_p99']:.1f} GUPS  "
-            f"(path {r['path']} K={r['views_per_pass']} ZU={r['z_unroll']} TX={r['tile_x']}) kernels {r['kernels']}")
+            f"(path {r['path']} K={r['views_per_pass']} ZU={r['z_unroll']} TX={r['tile_x']}"
+            f"{' direct taps' if r.get('direct_taps') else ''}) kernels {r['kernels']}")
         results[form] = r
 
     # CPU baseline: the oracle on the centre block, on this host's cores.
@@ -247,7 +248,7 @@ def main():
     per_launch_ms = ms_bp / max(n_bp, 1)
     updates_per_launch = updates * args.steps / max(n_bp, 1)
     achieved = updates_per_launch * VALU_PER_UPDATE / (per_launch_ms * 1e-3) / 1e12
-    kernel = "backproject_kernel" if args.direct_taps else "backproject_lds_kernel"
+    kernel = "backproject_kernel" if head.get("direct_taps") else "backproject_lds_kernel"
     launch = f"K={head['views_per_pass']} ZU={head['z_unroll']} TX={head['tile_x']} split={args.tap_split}"
     traffic = measured_traffic(kernel, launch, wl.name) if head is results.get("fused_f32") else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_T, 3),
@@ -259,7 +260,7 @@ def main():
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {"path": r["path"], "dtype": r["dtype"], "views_per_pass": r["views_per_pass"],
-                           "z_unroll": r["z_unroll"], "tile_x": r["tile_x"],
+                           "z_unroll": r["z_unroll"], "tile_x": r["tile_x"], "direct_taps": r.get("direct_taps"),
                            "ms_per_step": round(float(r["step_ms"].mean()), 3),
                            "gups_p50": round(r["gups_p50"], 2), "gups_p99": round(r["gups_p99"], 2),
                            "gups_mean": round(r["gups_mean"], 2),

@@ -180,9 +180,12 @@ bp_status bp_set_options(bp_ctx ctx, int options);
  * Results are bit-identical for every share. */
 bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
 
-/* The choices the next call of size nx*ny*nz with n_views views will use. */
+/* The choices the next call of size nx*ny*nz with n_views views will use; any output may be NULL.
+ * direct_taps: 1 if the fused pass reads every tap through L1 (no LDS stage) -- set by
+ * BP_OPT_DIRECT_TAPS, or chosen for FP32 records on boxes of 2e8 voxels or more unless a tap
+ * split is set. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
-                        bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x);
+                        bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x, int *direct_taps);
 
 /*
  * Compose the projection matrices of a circular cone-beam orbit on the host

@@ -29,6 +29,12 @@ class Candidate:
     views_per_pass: int
     z_unroll: int
     tile_x: int = 64
+    tap_split: int = -1        # fused path: views of every 8 read directly (-1 = tuned, 8 = all)
+    direct_taps: bool = False  # fused path: no LDS stage at all
+
+    def key(self) -> str:
+        return (f"{self.path}/{self.views_per_pass}/{self.z_unroll}/{self.tile_x}/"
+                f"{'direct' if self.direct_taps else self.tap_split}")
 
 
 @dataclass(frozen=True)
@@ -52,14 +58,18 @@ class Result:
     timings_ms: dict = field(default_factory=dict)  # "path/K/ZU/TX" -> median ms
 
 
-def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, txs=TX_CANDIDATES, include_plain=True):
-    """Plain passes (64-wide tiles), fused passes over K x ZU x tile width, and fused passes on the
-    caller's images (16- and 64-wide tiles)."""
+def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, txs=TX_CANDIDATES, include_plain=True,
+               splits=(-1,), include_direct_taps=True):
+    """Plain passes (64-wide tiles), fused passes over K x ZU x tile width x share of directly read
+    views (and with no LDS stage), and fused passes on the caller's images (16- and 64-wide tiles)."""
     zus = [zu for zu in zus if zu <= max(problem.nz, 1)]
     out = []
     if include_plain:
         out += [Candidate("plain", 1, zu, 64) for zu in zus]
-    out += [Candidate("fused", k, zu, tx) for k in ks if k <= problem.n_views for zu in zus for tx in txs]
+    fused = [(k, zu, tx) for k in ks if k <= problem.n_views for zu in zus for tx in txs]
+    out += [Candidate("fused", k, zu, tx, sp) for k, zu, tx in fused for sp in splits]
+    if include_direct_taps:
+        out += [Candidate("fused", k, zu, tx, -1, True) for k, zu, tx in fused]
     out += [Candidate("fused_direct", k, zu, tx) for k in ks if k <= problem.n_views for zu in zus
             for tx in txs if tx in (16, 64)]
     return out
@@ -71,14 +81,15 @@ def search(problem: Problem, time_fn, cands=None, reps: int = 3, warmup: int = 1
     if not cands:
         raise ValueError("no candidates to time")
     timings = {}
+    by_key = {}
     for c in cands:
         for _ in range(warmup):
             time_fn(c)
         ms = statistics.median(time_fn(c) for _ in range(reps))
-        timings[f"{c.path}/{c.views_per_pass}/{c.z_unroll}/{c.tile_x}"] = ms
+        timings[c.key()] = ms
+        by_key[c.key()] = c
     best_key = min(timings, key=timings.get)
-    path, k, zu, tx = best_key.split("/")
-    return Result(Candidate(path, int(k), int(zu), int(tx)), timings)
+    return Result(by_key[best_key], timings)
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:
@@ -106,7 +117,7 @@ def device_timer(ctx, volume, projections, matrices, voxel_size, origin, torch):
     """A ``time_fn`` that runs one call on the device and returns its time in ms (HIP events)."""
 
     def run(c: Candidate) -> float:
-        ctx.set_tuning(c.path, c.views_per_pass, c.z_unroll, c.tile_x)
+        apply(ctx, c)
         s = torch.cuda.current_stream()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -136,7 +147,10 @@ def tune_on_device(ctx, volume, projections, matrices, voxel_size, origin, cands
 
 
 def apply(ctx, cand: Candidate) -> None:
+    """Set the candidate's choices on a context (its options other than the tap mode are reset)."""
     ctx.set_tuning(cand.path, cand.views_per_pass, cand.z_unroll, cand.tile_x)
+    ctx.set_options(direct_taps=cand.direct_taps)
+    ctx.set_tap_split(cand.tap_split)
 
 
 def _csv_ints(s):
@@ -159,6 +173,8 @@ def main(argv=None):
     ap.add_argument("--zus", default="4,8")
     ap.add_argument("--txs", default="8,16,32,64")
     ap.add_argument("--plain", action="store_true", help="also time the plain path")
+    ap.add_argument("--splits", default="-1", help="shares of directly read views to try (-1 = tuned)")
+    ap.add_argument("--no-direct-taps", action="store_true", help="skip the candidates without an LDS stage")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     args = ap.parse_args(argv)
@@ -173,7 +189,8 @@ def main(argv=None):
     v = wl.volume
     vol = torch.zeros((v.L,) * 3, dtype=torch.float32, device=dev)
     problem = Problem(v.L, v.L, v.L, wl.scanner.n_views, dtype, wl.scanner.W, wl.scanner.H)
-    cands = candidates(problem, _csv_ints(args.ks), _csv_ints(args.zus), _csv_ints(args.txs), args.plain)
+    cands = candidates(problem, _csv_ints(args.ks), _csv_ints(args.zus), _csv_ints(args.txs), args.plain,
+                       _csv_ints(args.splits), not args.no_direct_taps)
     with bp.Context(wl.scanner.W, wl.scanner.H, dtype) as ctx:
         res = search(problem, device_timer(ctx, vol, proj, mats, v.voxel_size, v.origin, torch), cands, args.reps)
     updates = v.L ** 3 * wl.scanner.n_views

@@ -61,7 +61,8 @@ SIGNATURES = {
     "bp_set_options": (_c_int, [_vp, _c_int]),
     "bp_set_tap_split": (_c_int, [_vp, _c_int]),
     "bp_query_plan": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
-                               ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]),
+                               ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
+                               ctypes.POINTER(_c_int)]),
     "bp_circular_matrices": (_c_int, [_vp, _c_int, _c_double, _c_double, _c_double, _c_int, _c_int, _vp, _vp]),
     "bp_enable_timing": (_c_int, [_vp, _c_int]),
     "bp_kernel_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong)]),
@@ -122,6 +123,7 @@ class Plan:
     views_per_pass: int
     z_unroll: int
     tile_x: int
+    direct_taps: bool = False
 
 
 class Context:
@@ -225,10 +227,10 @@ class Context:
         return ms.value, n.value
 
     def plan(self, nx, ny, nz, n_views) -> Plan:
-        p, k, z, t = _c_int(), _c_int(), _c_int(), _c_int()
+        p, k, z, t, d = _c_int(), _c_int(), _c_int(), _c_int(), _c_int()
         self._check(lib().bp_query_plan(self._h, nx, ny, nz, n_views, ctypes.byref(p), ctypes.byref(k),
-                                        ctypes.byref(z), ctypes.byref(t)), "bp_query_plan")
-        return Plan(PATH_NAMES[p.value], k.value, z.value, t.value)
+                                        ctypes.byref(z), ctypes.byref(t), ctypes.byref(d)), "bp_query_plan")
+        return Plan(PATH_NAMES[p.value], k.value, z.value, t.value, bool(d.value))
 
     def backproject(self, volume, projections, matrices, voxel_size, origin, stream=None) -> None:
         """Accumulate ``projections`` (N, H, W) into ``volume`` (nz, ny, nx), asynchronously on ``stream``.

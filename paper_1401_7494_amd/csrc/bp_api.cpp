@@ -161,6 +161,7 @@ struct Plan {
     int k;
     int zu;
     int tx;
+    bool direct_taps = false;  // fused path: every tap through L1, no LDS stage
 };
 
 // Tuned defaults (measured on MI355X at L = 512, 496 views); BP_PATH_AUTO
@@ -177,11 +178,18 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
         p.path = voxels < 8.0 * ctx->cfg.det_width * (double)ctx->cfg.det_height ? BP_PATH_FUSED_DIRECT
                                                                                   : BP_PATH_FUSED;
     }
+    // Staged or direct taps for the fused pass.  FP32 records of a fine grid (many voxels per
+    // detector pixel) reuse the L1 well enough that the direct loads win: measured at 1248 x 960
+    // pixels and a 256 mm field of view, the staged-and-direct split is ahead at L = 512 and
+    // behind from L = 640 up; compact records favour the split at every size.
+    const bool compact = ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING);
+    const double voxels = (double)nx * (double)ny * (double)nz;
+    p.direct_taps = p.path == BP_PATH_FUSED &&
+                    ((ctx->options & BP_OPT_DIRECT_TAPS) || (!compact && ctx->tap_split < 0 && voxels >= 2.0e8));
     p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
     if (p.k <= 0) {
-        const bool compact = ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING);
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
-        else if (ctx->options & BP_OPT_DIRECT_TAPS) p.k = compact ? 64 : 32;  // 8-byte records halve the footprint
+        else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
         else p.k = compact ? 128 : 64;  // LDS-staged taps (measured at L = 512, 496 views)
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
@@ -314,7 +322,7 @@ bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths)
 }
 
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path* path, int* views_per_pass,
-                        int* z_unroll, int* tile_x)
+                        int* z_unroll, int* tile_x, int* direct_taps)
 {
     if (!ctx || nx < 1 || ny < 1 || nz < 1 || n_views < 1) return BP_ERR_INVALID_ARG;
     const Plan p = plan_for(ctx, nx, ny, nz, n_views);
@@ -322,6 +330,7 @@ bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path
     if (views_per_pass) *views_per_pass = p.k;
     if (z_unroll) *z_unroll = p.zu;
     if (tile_x) *tile_x = p.tx;
+    if (direct_taps) *direct_taps = p.direct_taps ? 1 : 0;
     return BP_OK;
 }
 
@@ -395,7 +404,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
         layout = bp::Layout::Patch16;
     // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
-    const bool lds = staged_taps(ctx, layout, W, H);
+    const bool lds = !plan.direct_taps && staged_taps(ctx, layout, W, H);
     const bool culled = (layout != bp::Layout::Checked || plan.path == BP_PATH_FUSED_DIRECT) && !lds &&
                         !(ctx->options & BP_OPT_NO_CULL);
     const long tiles = bp::n_tiles(nx, ny, nz, plan.zu, plan.tx);

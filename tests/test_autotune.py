@@ -26,7 +26,7 @@ def test_search_picks_the_fastest_by_median():
         return base * (5.0 if calls[c] == 2 else 1.0)
 
     r = at.search(P, fake, reps=3, warmup=1)
-    assert r.best == at.Candidate("fused", 64, 8, 16)
+    assert r.best == at.Candidate("fused", 64, 8, 16)  # the staged (tuned split) candidate comes first
     assert all(v == 4 for v in calls.values())  # 1 warm-up + 3 timed
     assert len(r.timings_ms) == len(at.candidates(P))
 
@@ -38,5 +38,15 @@ def test_cache_round_trip(tmp_path):
     assert at.lookup(key, path) is None
     at.store(key, r, path)
     assert at.lookup(key, path) == at.Candidate("fused", 16, 4, 8)
+    r2 = at.Result(at.Candidate("fused", 32, 8, 16, 4, True), {})
+    at.store(P.key("dev2"), r2, path)
+    assert at.lookup(P.key("dev2"), path) == at.Candidate("fused", 32, 8, 16, 4, True)
     at.store(P.key("other"), at.Result(at.Candidate("plain", 1, 8)), path)
     assert at.lookup(key, path) == at.Candidate("fused", 16, 4, 8)
+
+
+def test_split_and_direct_candidates():
+    cands = at.candidates(P, ks=(32, 64), zus=(8,), txs=(16,), include_plain=False, splits=(-1, 0, 4))
+    fused = [c for c in cands if c.path == "fused"]
+    assert {(c.tap_split, c.direct_taps) for c in fused} == {(-1, False), (0, False), (4, False), (-1, True)}
+    assert len({c.key() for c in cands}) == len(cands)  # keys are unique

@@ -212,6 +212,21 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
+        # staged or direct taps: FP32 records stage at L = 512, read directly on finer, larger grids
+        ctx.set_tuning("auto", 0, 0, 0)
+        p = ctx.plan(512, 512, 512, 496)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, False)
+        p = ctx.plan(640, 640, 640, 496)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, True)
+        ctx.set_tap_split(4)  # an explicit split keeps the stage
+        assert not ctx.plan(1024, 1024, 1024, 496).direct_taps
+        ctx.set_tap_split(-1)
+        ctx.set_options(direct_taps=True)
+        p = ctx.plan(512, 512, 512, 496)
+        assert (p.views_per_pass, p.direct_taps) == (32, True)
+    with bp.Context(1248, 960, "bf16") as ctx:
+        p = ctx.plan(1024, 1024, 1024, 496)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
 
 
 # ---------------------------------------------------------------------------

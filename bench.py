@@ -43,12 +43,18 @@ COUNTERS_MD = "profiles/backproject_fused_f32_l512_v496_counters.md"
 
 
 def kernel_source_sha():
+    """SHA-256 of the kernel sources with comments and white space removed (so that an edit of a
+    comment keeps a counter record valid, while any change of the code does not)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -7,20 +7,25 @@
 //
 // GPU mapping
 //   * One thread owns ZU voxels of one (x, y) column at consecutive z; a
-//     wavefront spans 64 consecutive x, so every volume load/store is one
-//     coalesced 256-byte row segment.  Voxels stay in registers for all the
-//     views of a pass; the volume is read and written once per pass (the
-//     8 bytes per voxel update of Sec. 4.2 divided by the views per pass).
+//     256-thread block covers TX x (256 / TX) columns (16 x 16 by default), a
+//     wavefront TX x (64 / TX), so volume loads and stores are whole row
+//     segments.  Voxels stay in registers for all the views of a pass; the
+//     volume is read and written once per pass (the 8 bytes per voxel update
+//     of Sec. 4.2 divided by the views per pass).
 //   * View constants are wave-uniform: scalar loads, no VGPRs.
 //   * Part 1 hoists the (x, y) terms out of the z loop: u, v, w cost one FMA
 //     each per voxel; 1/w is the hardware reciprocal (Sec. 5.1 makes the same
-//     substitution on the CPUs).
-//   * Part 2 uses buffer loads with 32-bit offsets.  The fused pass reads a
-//     staging copy of the views in which every pixel carries the four
-//     coefficients of its bilinear patch and the detector has a one-pixel zero
-//     border (the zero-padded copy of Sec. 5.1.1): the position is clamped
-//     into the bordered frame, so the taps need no tests, and one aligned
-//     16-byte (8-byte for 16-bit data) load replaces the four taps.
+//     substitution on the CPUs).  For views whose u and w do not depend on z
+//     (circular orbits) the column, 1/w and 1/w^2 are formed once per column.
+//   * Part 2: the fused pass reads a staging copy of the views in which every
+//     pixel carries the four coefficients of its bilinear patch and the
+//     detector has a one-pixel zero border (the zero-padded copy of Sec.
+//     5.1.1): the position is clamped into the bordered frame, so the taps
+//     need no tests, and one 16-byte (8-byte for 16-bit data) record replaces
+//     the four taps.  The record comes either from L1 (an indexed buffer
+//     load) or from the block tile's footprint staged in LDS; the default
+//     pass mixes the two by view.  The plain and direct-fused passes read the
+//     caller's images with per-tap bounds tests instead.
 //   * A view whose matrix puts some voxel of the box behind (or too near) the
 //     source plane takes a guarded branch that zeroes such contributions; the
 //     branch is uniform per view, decided once per call.

@@ -427,6 +427,15 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
         acc[i] = 0.0f;
     }
     const uint32_t* cull_row = cull ? cull + (size_t)tile * cull_words : nullptr;
+    // Passes on the caller's images (the plain pass reads one view per pass): load the volume's
+    // old values before the taps, so that the read overlaps them (x, y are clamped: in bounds).
+    float old[ZU];
+    if constexpr (!PADDED) {
+        const size_t plane = (size_t)box.nx * (size_t)box.ny;
+        const size_t col = (size_t)y * box.nx + x;
+#pragma unroll
+        for (int i = 0; i < ZU; ++i) old[i] = z0 + i < box.nz ? vol[(size_t)(z0 + i) * plane + col] : 0.0f;
+    }
 
     for (int k = 0; k < n_views; ++k) {
         if (cull_row) {
@@ -471,7 +480,8 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
         for (int i = 0; i < ZU; ++i) {
             if (z0 + i < box.nz) {
                 float* p = vol + (size_t)(z0 + i) * plane + col;
-                *p += acc[i];
+                if constexpr (!PADDED) *p = old[i] + acc[i];  // the same sum as += (no other writer)
+                else *p += acc[i];
             }
         }
     }

@@ -101,6 +101,12 @@ def parse():
     return ap.parse_args()
 
 
+def _device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": torch.cuda.get_device_name(0), "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count, "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -298,7 +304,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fdk_preprocessing": fdk,
-        "device": torch.cuda.get_device_name(0),
+        "device": _device_info(torch),
     }
     print(json.dumps(line), flush=True)
 

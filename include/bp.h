@@ -32,10 +32,13 @@
  * Ownership and concurrency: the caller owns every array.  volume,
  * projections and matrices are DEVICE pointers on the context's device; they
  * must stay valid and unmodified until the work enqueued on `stream` has
- * completed.  A context owns device scratch (per-view constants and the
- * zero-padded staging copy of the projections) that every call reuses, so
- * calls on one context must not overlap: use one context per stream that
- * runs concurrently.  Contexts are cheap.
+ * completed.  A context owns device scratch that every call reuses: per-view
+ * constants, the staging copy of one pass of views (about K (W+2)(H+2) x 16
+ * bytes, 8 for compact 16-bit records: 1.2 GB at K = 64 and 1248 x 960), the
+ * footprint table or clipping mask of the block tiles.  It grows on demand
+ * (a growth waits for the device) and is freed by bp_destroy, so calls on one
+ * context must not overlap: use one context per stream that runs
+ * concurrently.  Creating a context allocates nothing.
  *
  * Errors: argument checks run on the host before anything is enqueued; a
  * call that returns anything but BP_OK has enqueued nothing.  Device faults
@@ -86,11 +89,11 @@ typedef struct {
     int det_height;       /* H, detector rows (960) */
     bp_dtype proj_dtype;  /* storage type of the projections */
     bp_path path;         /* BP_PATH_AUTO picks a path per call */
-    int views_per_pass;   /* K for BP_PATH_FUSED; 0 = tuned */
+    int views_per_pass;   /* K for the fused paths; 0 = tuned */
     int z_unroll;         /* voxels per thread along z (1, 2, 4 or 8); 0 = tuned */
     int tile_x;           /* columns along x per 256-thread block (8, 16, 32 or 64; the block is
-                             tile_x x 256/tile_x columns); 0 = tuned.  BP_PATH_PLAIN takes 16
-                             or 64 (others give 64). */
+                             tile_x x 256/tile_x columns); 0 = tuned.  The caller's-image
+                             paths (PLAIN, FUSED_DIRECT) take 16 or 64 (others give 64). */
 } bp_config;
 
 /* Fill *cfg with defaults: device 0, 1248 x 960, FP32, AUTO, tuned K, z_unroll and tile_x. */

@@ -226,10 +226,11 @@ class GpuExecutor:
         bpp = 4 if r.dtype == "f32" else 2
         vol = 4 * r.L ** 3
         proj = r.n_views * sc.W * sc.H * bpp
-        k = min(r.n_views, self.tuning[0] or 32)
+        k = min(r.n_views, self.tuning[0] or (64 if r.dtype == "f32" else 128))  # the library's default K
         raw = r.n_views * sc.W * sc.H * 4 if self.fast_inputs else 0
         staging = k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
-        cull = (r.L // 16) * (r.L // 16) * (r.L // 4 + 1) * ((r.n_views + 31) // 32) * 4
+        tiles = (r.L // 16 + 1) * (r.L // 16 + 1) * (r.L // 8 + 1)
+        cull = tiles * max((r.n_views + 31) // 32 * 4, k * 8)  # clipping mask or footprint table
         gen = 6 * 62 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (62 views at a time)
         return vol + proj + raw + staging + cull + gen
 

@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--no-column", action="store_true", help="time without the column specialisation")
     ap.add_argument("--direct-taps", action="store_true", help="fused forms read every tap directly (no LDS stage)")
     ap.add_argument("--tap-split", type=int, default=-1, help="views of every 8 read directly in a staged pass (-1 = tuned)")
+    ap.add_argument("--staging", default="auto", choices=("auto", "serial", "overlap"),
+                    help="stage each pass just before it, or the next pass while one runs (auto: tuned)")
     ap.add_argument("--no-fdk", action="store_true", help="skip timing the FDK pre-processing of the stack")
     ap.add_argument("--cpu-block", type=int, default=320,
                     help="edge of the centre block the oracle times (about 10 s of FP64 work on 16 threads)")
@@ -112,7 +114,7 @@ def log(msg):
 
 
 def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, tx=0, no_cull=False,
-              no_column=False, order="region", region_ax=0, direct_taps=False, tap_split=-1):
+              no_column=False, order="region", region_ax=0, direct_taps=False, tap_split=-1, staging="auto"):
     path, dt = form.rsplit("_", 1)
     path = {"direct": "fused_direct"}.get(path, path)
     proj = proj_by_dtype[dt]
@@ -123,7 +125,8 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
     stream = torch.cuda.current_stream(dev)
     ctx = bp.Context(W, H, dt)
     ctx.set_tuning(path, k, zu, tx)
-    ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax, direct_taps=direct_taps)
+    ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax, direct_taps=direct_taps,
+                    staging=staging)
     ctx.set_tap_split(tap_split)
     plan = ctx.plan(L, L, L, n)
     for _ in range(warmup):
@@ -217,7 +220,8 @@ def main():
     results = {}
     for form in forms:
         r = time_form(bp, torch, form, proj_by_dtype, P, v, args.steps, args.warmup, args.k, args.zu, args.tx,
-                      args.no_cull, args.no_column, args.order, args.region_ax, args.direct_taps, args.tap_split)
+                      args.no_cull, args.no_column, args.order, args.region_ax, args.direct_taps, args.tap_split,
+                      args.staging)
         ms = r["step_ms"]
         r["gups_mean"] = updates / (ms.mean() * 1e-3) / 1e9
         r["gups_p50"] = updates / (np.percentile(ms, 50) * 1e-3) / 1e9

@@ -33,16 +33,20 @@
  * projections and matrices are DEVICE pointers on the context's device; they
  * must stay valid and unmodified until the work enqueued on `stream` has
  * completed.  A context owns device scratch that every call reuses: per-view
- * constants, the staging copy of one pass of views (about K (W+2)(H+2) x 16
- * bytes, 8 for compact 16-bit records: 1.2 GB at K = 64 and 1248 x 960), the
- * footprint table or clipping mask of the block tiles.  It grows on demand
- * (a growth waits for the device) and is freed by bp_destroy, so calls on one
- * context must not overlap: use one context per stream that runs
- * concurrently.  Creating a context allocates nothing.
+ * constants, the staging copy of a pass of views (about K (W+2)(H+2) x 16
+ * bytes, 8 for compact 16-bit records: 1.2 GB at K = 64 and 1248 x 960; a
+ * call of two or more passes holds two such copies, see
+ * BP_OPT_OVERLAP_STAGING), the footprint tables or clipping mask of the block
+ * tiles, and a side stream with its events for the staging.  It grows on
+ * demand (a growth waits for the device) and is freed by bp_destroy, so
+ * calls on one context must not overlap: use one context per stream that
+ * runs concurrently.  Creating a context allocates nothing.
  *
- * Errors: argument checks run on the host before anything is enqueued; a
- * call that returns anything but BP_OK has enqueued nothing.  Device faults
- * surface at the caller's next synchronisation of `stream`.
+ * Errors: argument checks and scratch growth run on the host before anything
+ * is enqueued, and a call they reject has enqueued nothing.  A launch failure
+ * (BP_ERR_LAUNCH) can come after earlier passes were enqueued; the volume
+ * then holds a partial sum.  Device faults surface at the caller's next
+ * synchronisation of `stream`.
  * bp_last_error(ctx) describes the last failure of a call on that context.
  */
 #ifndef BP_H
@@ -108,7 +112,7 @@ bp_status bp_destroy(bp_ctx ctx);
 
 /*
  * Accumulate the back projection of n_views images into an L x L x L volume
- * (the spec entry point; equivalent to bp_backproject_box with
+ * (the cubic form of the Listing 1 interface; equivalent to bp_backproject_box with
  * nx = ny = nz = L).
  *
  *   volume      device FP32, L^3, ACCUMULATED (+=): zero it first for a fresh
@@ -157,6 +161,16 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     (bp_set_tap_split) that still read directly, so that the
  *                     pass draws on both paths at once.  Results are
  *                     bit-identical either way.
+ *   BP_OPT_SERIAL_STAGING   fused path: stage each pass's views on the caller's
+ *                     stream just before the pass.
+ *   BP_OPT_OVERLAP_STAGING  fused path, calls of two or more passes: stage pass
+ *                     p + 1 on a side stream of the context (default priority,
+ *                     ordered after the caller's stream by events) while pass p
+ *                     runs, into the other half of a two-pass staging buffer.
+ *                     Neither flag: overlapped for compact 16-bit records,
+ *                     serial for FP32 records (whose staging contends with the
+ *                     pass for the vector memory path).  Both flags: an error.
+ *                     Results are bit-identical in every case.
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of
@@ -175,6 +189,8 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_XCD_REGION_MASK (15 << BP_OPT_XCD_REGION_SHIFT)
 #define BP_OPT_XCD_REGION(ax) ((ax) << BP_OPT_XCD_REGION_SHIFT)
 #define BP_OPT_DIRECT_TAPS (1 << 9)
+#define BP_OPT_SERIAL_STAGING (1 << 10)
+#define BP_OPT_OVERLAP_STAGING (1 << 11)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* Fused path with LDS staging: of every 8 consecutive views of a pass, how many

@@ -188,14 +188,19 @@ class Context:
     OPT_PLAIN_ORDER = 16
     OPT_XCD_REGION_SHIFT = 5
     OPT_DIRECT_TAPS = 1 << 9
+    OPT_SERIAL_STAGING = 1 << 10
+    OPT_OVERLAP_STAGING = 1 << 11
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
-                    order: str = "region", region_ax: int = 0, direct_taps: bool = False):
+                    order: str = "region", region_ax: int = 0, direct_taps: bool = False,
+                    staging: str = "auto"):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
         projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
         each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices"); read every tap
-        of the fused path directly instead of staging most views' footprints through LDS."""
+        of the fused path directly instead of staging most views' footprints through LDS; stage the
+        next pass while one runs ("overlap"), just before it ("serial") or as tuned ("auto":
+        overlapped for compact 16-bit records)."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
                  | (self.OPT_WIDE_STAGING if wide_staging else 0))
         if order == "plain":
@@ -207,6 +212,12 @@ class Context:
         flags |= int(region_ax) << self.OPT_XCD_REGION_SHIFT
         if direct_taps:
             flags |= self.OPT_DIRECT_TAPS
+        if staging not in ("auto", "serial", "overlap"):
+            raise ValueError(f"staging must be auto, serial or overlap, not {staging!r}")
+        if staging == "serial":
+            flags |= self.OPT_SERIAL_STAGING
+        elif staging == "overlap":
+            flags |= self.OPT_OVERLAP_STAGING
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     def set_tap_split(self, direct_eighths: int = -1):

@@ -228,9 +228,10 @@ class GpuExecutor:
         proj = r.n_views * sc.W * sc.H * bpp
         k = min(r.n_views, self.tuning[0] or (64 if r.dtype == "f32" else 128))  # the library's default K
         raw = r.n_views * sc.W * sc.H * 4 if self.fast_inputs else 0
-        staging = k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
+        # compact records: two passes staged, the next one while one runs
+        staging = (2 if r.n_views > k and r.dtype != "f32" else 1) * k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
         tiles = (r.L // 16 + 1) * (r.L // 16 + 1) * (r.L // 8 + 1)
-        cull = tiles * max((r.n_views + 31) // 32 * 4, k * 8)  # clipping mask or footprint table
+        cull = tiles * max((r.n_views + 31) // 32 * 4, 2 * k * 8)  # clipping mask or footprint tables
         gen = 6 * 62 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (62 views at a time)
         return vol + proj + raw + staging + cull + gen
 

@@ -20,7 +20,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(bp_[a-z_0-9]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_create_backproject_destroy_entry_points():
     names = declared_functions()
     for n in ("bp_create", "bp_backproject", "bp_destroy"):
         assert n in names

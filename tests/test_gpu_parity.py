@@ -182,6 +182,7 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_options(h, 1 << 12) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_options(h, 3 << 5) == bp.BP_ERR_INVALID_ARG  # region split of 3 along x
+        assert L.bp_set_options(h, (1 << 10) | (1 << 11)) == bp.BP_ERR_INVALID_ARG  # serial and overlapped
         torch.cuda.synchronize()
     assert not vol.any()
 
@@ -295,7 +296,8 @@ def test_parity_l512_sampled(dtype, compact):
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1):
+              order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1,
+              staging="auto"):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -304,7 +306,7 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
-                        direct_taps=direct_taps, wide_staging=wide_staging)
+                        direct_taps=direct_taps, wide_staging=wide_staging, staging=staging)
         ctx.set_tap_split(tap_split)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
@@ -395,6 +397,51 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
                               tap_split=split, **kw)
                 assert np.array_equal(a, b), (shape, vs, kw, tx, zu, split)
             assert np.abs(a).max() > 0
+
+
+@pytest.mark.parametrize("dtype,wide", [("f32", False), ("bf16", False), ("bf16", True)])
+def test_staging_overlap_is_bit_identical(dtype, wide):
+    """Staging the next pass on the context's side stream while the current pass runs gives the same
+    bits as staging each pass just before it: many passes (both halves of the staging buffer reused),
+    a ragged last pass, LDS-staged and direct taps, and a caller on a non-default stream whose earlier
+    work the side stream must wait for."""
+    sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(78))
+    if dtype != "f32":
+        proj = proj.to(gc.TORCH_DTYPE[dtype])
+    P32 = gc.product_matrices(sc)
+    shape, vs = (40, 70, 130), 2.0
+    origin = _box_origin(shape, vs)
+    for k in (4, 13, 28):  # 8, 3 and 2 passes
+        for direct in (False, True):
+            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, wide_staging=wide,
+                          direct_taps=direct, staging="serial")
+            b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, wide_staging=wide,
+                          direct_taps=direct, staging="overlap")
+            assert np.array_equal(a, b), (k, direct)
+            assert np.abs(a).max() > 0
+    # a side stream of the caller's: the projections are written there just before the call, and two
+    # calls accumulate into one volume; against the same two calls staged serially on the default stream
+    dev = torch.device("cuda:0")
+    m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
+    src = proj.to(dev).contiguous()
+    vols = []
+    for serial in (True, False):
+        st = torch.cuda.current_stream(dev) if serial else torch.cuda.Stream(device=dev)
+        with bp.Context(sc.W, sc.H, dtype) as ctx:
+            ctx.set_tuning("fused", 4, 8, 16)
+            ctx.set_options(wide_staging=wide, staging="serial" if serial else "overlap")
+            vol = torch.zeros(shape, dtype=torch.float32, device=dev)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(st):
+                p = torch.empty_like(src)
+                p.copy_(src)
+                ctx.backproject(vol, p, m, vs, origin, st)
+                ctx.backproject(vol, p, m, vs, origin, st)
+            st.synchronize()
+        vols.append(vol)
+    assert torch.equal(vols[0], vols[1])
+    assert float(vols[0].abs().max()) > 0
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])

@@ -607,13 +607,18 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             const float r2 = src.weight_column(view, r);
             const float dt = c.p[6] * r;
             const float tb = fmaf(vxy, r, 1.0f);
-            const int cb = base + c0;
+            // byte offsets, so that the row's address is one 24-bit multiply-add
+            const uint32_t row_b = (uint32_t)fw * (uint32_t)sizeof(Rec);
+            const uint32_t cb_b = (uint32_t)(base + c0) * (uint32_t)sizeof(Rec);
+            const char* lds_b = reinterpret_cast<const char*>(lds);
 #pragma unroll
             for (int i = 0; i < ZU; ++i) {
                 const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), t_lo, t_hi);
                 const int r0 = (int)t;
                 const float fy = __builtin_amdgcn_fractf(t);
-                acc[i] = fmaf(Src::eval(lds[__mul24(r0, fw) + cb], fx, fy), r2, acc[i]);
+                const Rec* q = static_cast<const Rec*>(
+                    __builtin_assume_aligned(lds_b + (__umul24((uint32_t)r0, row_b) + cb_b), sizeof(Rec)));
+                acc[i] = fmaf(Src::eval(*q, fx, fy), r2, acc[i]);
             }
         } else {  // safe
 #pragma unroll

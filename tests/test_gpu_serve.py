@@ -18,11 +18,12 @@ def small_volume(r):
 
 def test_results_are_the_same_alone_and_in_the_mix():
     rng = np.random.default_rng(1405)
-    reqs = [synth.Request(i, 0.002 * i, int(rng.choice([32, 48, 64])), int(rng.choice([12, 24, 36])),
+    # all arrive at once, so that four run together whatever the device's speed
+    reqs = [synth.Request(i, 0.0, int(rng.choice([32, 48, 64])), int(rng.choice([12, 24, 36])),
                           str(rng.choice(["f32", "f16"])), 100000 + i) for i in range(8)]
     kw = dict(keep_results=True, scanner_fn=small_scanner, volume_fn=small_volume)
     mix = serve.Server(serve.GpuExecutor(**kw), budget_bytes=8 * serve.GIB, max_inflight=4).run(reqs)
-    assert len(mix.completed) == 8 and mix.peak_inflight > 1
+    assert len(mix.completed) == 8 and mix.peak_inflight == 4
     alone = {}
     for r in reqs:
         rep = serve.Server(serve.GpuExecutor(**kw), budget_bytes=8 * serve.GIB, max_inflight=1).run([r])

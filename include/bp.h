@@ -171,6 +171,10 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     serial for FP32 records (whose staging contends with the
  *                     pass for the vector memory path).  Both flags: an error.
  *                     Results are bit-identical in every case.
+ *   BP_OPT_STAGE_RECORDS  fused path, FP32 projections: copy the LDS footprints
+ *                     as 16-byte patch records rather than as the caller's FP32
+ *                     pixels (from which each update then forms its patch with
+ *                     the staging copy's own FP32 operations).  Bit-identical.
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of
@@ -191,6 +195,7 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_DIRECT_TAPS (1 << 9)
 #define BP_OPT_SERIAL_STAGING (1 << 10)
 #define BP_OPT_OVERLAP_STAGING (1 << 11)
+#define BP_OPT_STAGE_RECORDS (1 << 12)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* Fused path with LDS staging: of every 8 consecutive views of a pass, how many

@@ -190,11 +190,12 @@ class Context:
     OPT_DIRECT_TAPS = 1 << 9
     OPT_SERIAL_STAGING = 1 << 10
     OPT_OVERLAP_STAGING = 1 << 11
+    OPT_STAGE_RECORDS = 1 << 12
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
                     order: str = "region", region_ax: int = 0, direct_taps: bool = False,
-                    staging: str = "auto"):
+                    staging: str = "auto", stage_records: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
         projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
         each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices"); read every tap
@@ -218,6 +219,8 @@ class Context:
             flags |= self.OPT_SERIAL_STAGING
         elif staging == "overlap":
             flags |= self.OPT_OVERLAP_STAGING
+        if stage_records:
+            flags |= self.OPT_STAGE_RECORDS
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     def set_tap_split(self, direct_eighths: int = -1):

@@ -374,7 +374,7 @@ bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
-                    BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS | BP_OPT_SERIAL_STAGING | BP_OPT_OVERLAP_STAGING))
+                    BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS | BP_OPT_SERIAL_STAGING | BP_OPT_OVERLAP_STAGING | BP_OPT_STAGE_RECORDS))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
     if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
@@ -454,6 +454,9 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     // compact records only (L = 512, 496 views: BF16 2068 -> 2151 GUPS); the FP32 staging kernel
     // contends with the pass for the vector memory path, and the pass slows by what the overlap hides.
     const bool staged = layout != bp::Layout::Checked;
+    // FP32 input: the LDS stage holds the caller's pixels (a quarter of the bytes of the records)
+    const bool raw_stage = lds && layout == bp::Layout::Patch && dt == bp::Dtype::F32 &&
+                           !(ctx->options & BP_OPT_STAGE_RECORDS);
     const bool overlap = staged && n_views > plan.k && !(ctx->options & BP_OPT_SERIAL_STAGING) &&
                          (layout == bp::Layout::Patch16 || (ctx->options & BP_OPT_OVERLAP_STAGING));
     const int halves = overlap ? 2 : 1;
@@ -531,8 +534,8 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
             if (lds) {
                 e = timed(ctx, 2, ss, [&] {
-                    return bp::launch_footprint(ctx->d_views + k0, kc, box, plan.zu, plan.tx, W, H,
-                                                bp::kStageRecords, split, fp, ss);
+                    return bp::launch_footprint(ctx->d_views + k0, kc, box, plan.zu, plan.tx, W, H, raw_stage,
+                                                split, fp, ss);
                 });
                 if (e != hipSuccess)
                     return fail(ctx, BP_ERR_LAUNCH, std::string("footprint kernel: ") + hipGetErrorString(e));
@@ -542,14 +545,15 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                 return fail(ctx, BP_ERR_LAUNCH, "cannot order the pass after its staging");
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
-                                              pad, W, H, cull, xcd_order, inv_scale, fp, s);
+                                              pad, W, H, cull, xcd_order, inv_scale, fp,
+                                              raw_stage ? static_cast<const float*>(src_views) : nullptr, s);
             });
             if (e == hipSuccess && overlap && hipEventRecord(ctx->ev_done[half], s) != hipSuccess)
                 return fail(ctx, BP_ERR_LAUNCH, "cannot record the end of a pass");
         } else {
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
-                                              src_views, W, H, cull, xcd_order, nullptr, nullptr, s);
+                                              src_views, W, H, cull, xcd_order, nullptr, nullptr, nullptr, s);
             });
         }
         if (e != hipSuccess)

@@ -71,11 +71,13 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 // columns.  xcd_order: deal contiguous z-ranges of tiles to the 8 XCDs.
 // footprints (patch layouts only; null = read the taps directly): the pass's
 // footprint table from launch_footprint, [tile][view] -- the taps are then
-// staged through LDS.
+// staged through LDS.  raw (Layout::Patch with footprints only; else null): the
+// caller's FP32 images of the pass, [n][H][W] -- staged footprints are then
+// copied into LDS as pixels (footprint table made with raw = true).
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
                               const Cull& cull, int xcd_order, const float* inv_scale, const uint2* footprints,
-                              hipStream_t s);
+                              const float* raw, hipStream_t s);
 
 // Patch records a block of the staged pass holds one view's footprint in (LDS):
 // footprints of up to 64 columns by 32 rows.
@@ -88,8 +90,10 @@ constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
 
 // Footprint table of one pass: n views (view constants vc[0, n)), every tile;
 // views with k % 8 < direct_eighths are marked to read their taps directly.
+// raw: footprints sized for staging FP32 pixels (fw < 64, fh < 32) rather
+// than patch records (fw <= 64, fh <= 32, fw fh <= kStageRecords).
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            int cap, int direct_eighths, uint2* out, hipStream_t s);
+                            bool raw, int direct_eighths, uint2* out, hipStream_t s);
 
 // Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
 inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)

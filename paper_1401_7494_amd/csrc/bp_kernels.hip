@@ -45,6 +45,9 @@ constexpr int kXcds = 8;     // MI355X: 8 XCDs, consecutive workgroups go to con
 // LDS-staged taps: one footprint row per wave and slot, one column per lane
 constexpr int kStageSlots = 8;
 constexpr int kStageMaxWidth = 64, kStageMaxHeight = 4 * kStageSlots;
+// FP32 pixels staged for the footprint of fw x fh patches: (fw + 1) x (fh + 1) pixels, at most 64 x 32,
+// in rows of a fixed stride so that a patch's four pixels are two ds_read2_b32 with immediate offsets.
+constexpr int kRawStride = kStageMaxWidth + 1, kRawRows = kStageMaxHeight;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {
@@ -144,10 +147,14 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 // Indexed buffer load: address = base + vindex * stride; vindex >= num_records reads 0.
 __device__ f32x4_t struct_buffer_load_f32x4(i32x4_t rsrc, int vindex, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.struct.buffer.load.v4f32");
+// Byte-offset buffer load of one FP32 value; offsets >= num_records read 0.
+__device__ float raw_buffer_load_f32(i32x4_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.f32");
 
 struct PatchSource {
     const uint8_t* base;
     int W, H;
+    static constexpr bool kRawStage = false;  // staged footprints copy patch records
 
     struct View {
         i32x4_t rs;
@@ -242,6 +249,40 @@ struct PatchSource {
     }
 };
 
+// FP32 projections: directly read views take patch records as PatchSource
+// does; a staged footprint is copied into LDS as the caller's FP32 pixels (a
+// quarter of the bytes of its records), and each update forms its patch's
+// coefficients from the four pixels with the same FP32 operations as
+// patch_kernel, so both paths give the same bits.
+struct RawPatchSource : PatchSource {
+    const float* raw;  // the caller's images of the pass, [n][H][W]
+    static constexpr bool kRawStage = true;
+
+    // View k's pixels as a byte-addressed buffer of W H FP32 values: offsets past the end read 0.
+    __device__ __forceinline__ i32x4_t raw_view(int k) const
+    {
+        const uint64_t a = (uint64_t)(raw + (size_t)k * W * H);
+        i32x4_t rs;
+        rs.x = (int)(uint32_t)a;
+        rs.y = (int)((uint32_t)(a >> 32) & 0xffffu);
+        rs.z = (int)((uint32_t)W * (uint32_t)H * 4u);
+        rs.w = 0x00020000;
+        return rs;
+    }
+
+    // The record of patch (r, c) from the pixels (r, c), (r, c+1), (r+1, c), (r+1, c+1).
+    static __device__ __forceinline__ Rec record(float a, float b, float cc, float d)
+    {
+        const float dx = b - a;
+        Rec q;
+        q.x = a;
+        q.y = dx;
+        q.z = cc - a;
+        q.w = (d - cc) - dx;
+        return q;
+    }
+};
+
 // Compact bilinear-patch layout for 16-bit projections: the same four
 // coefficients as PatchSource, stored as FP16 (8 bytes per record) after
 // scaling view k by a power of two, 2^e_k, chosen from the view's largest
@@ -257,6 +298,7 @@ struct Patch16Source {
     const uint8_t* base;
     int W, H;
     const float* inv_scale;  // 2^-e_k per view of the pass
+    static constexpr bool kRawStage = false;
 
     struct View {
         i32x4_t rs;
@@ -499,14 +541,25 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
 // pass, and the results are bit-identical to it.  Views whose footprint does
 // not fit the LDS buffer, and guarded views, read their taps directly.
 // ---------------------------------------------------------------------------
+template <class Src, bool RAW = Src::kRawStage>
+struct StageOf {
+    using type = typename Src::Rec;
+};
+template <class Src>
+struct StageOf<Src, true> {
+    using type = float;
+};
+
 template <class Src, int ZU, int TX>
 __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
     const uint2* __restrict__ fp, int xcd_order)
 {
     using Rec = typename Src::Rec;
+    constexpr bool kRaw = Src::kRawStage;
     static_assert(kStageMaxWidth * kStageMaxHeight == kStageRecords, "LDS stage shape");
-    __shared__ Rec lds[kStageRecords];
+    using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels
+    __shared__ StageT lds[kRaw ? kRawStride * kRawRows : kStageRecords];
     constexpr int TY = kBlock / TX;
     const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
     const int n_tiles = gx * gy * gz;
@@ -528,32 +581,69 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         acc[i] = 0.0f;
     }
     const uint2* fp_row = fp + (size_t)tile * n_views;
-    // Records of the next staged footprint, loaded while the current view is computed:
-    // footprint row wave + 4 j is slot j of that wave, one column per lane (fw <= 64 and
-    // fh <= 4 kStageSlots for every staged footprint).
-    Rec pre[kStageSlots];
+    // The next staged footprint, loaded while the current view is computed: footprint row
+    // wave + 4 j is slot j of that wave, one column per lane.  Records: fw <= 64 and fh <= 4
+    // kStageSlots; FP32 pixels: the fw + 1 columns and fh + 1 rows of the patches' corners,
+    // fw < 64 and fh < 4 kStageSlots (the footprint table keeps to these bounds).
+    StageT pre[kStageSlots];
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
     auto prefetch = [&](int k, uint2 f) {
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
-        const auto vw = src.view(k);
-        const int cols = src.cols();
-        const int g = (rmin + wave) * cols + cmin + lane;  // record index in the staging view
-        if (lane < fw) {
+        if constexpr (kRaw) {
+            // padded pixel (r, c) is detector pixel (c - 1, r - 1): byte offset ((r - 1) W + c - 1) 4,
+            // in 32-bit arithmetic, so rows above the detector wrap past the end and read 0 as rows
+            // below it do; columns off the detector are sent past the end (W H 4 < 2^31).
+            const int c = cmin + lane;
+            const bool col_ok = (lane <= fw) & (c >= 1) & (c <= src.W);
+            const uint32_t row_bytes = (uint32_t)src.W * 4u;
+            const uint32_t off0 = col_ok ? (uint32_t)(rmin - 1 + wave) * row_bytes + (uint32_t)(c - 1) * 4u
+                                         : 0x80000000u;
+            const i32x4_t rs = src.raw_view(k);
 #pragma unroll
             for (int j = 0; j < kStageSlots; ++j)
-                if (wave + 4 * j < fh) pre[j] = src.load(vw, g + 4 * j * cols);
+                if (wave + 4 * j <= fh)
+                    pre[j] = raw_buffer_load_f32(rs, (int)(off0 + (uint32_t)(4 * j) * row_bytes), 0, 0);
+        } else {
+            const auto vw = src.view(k);
+            const int cols = src.cols();
+            const int g = (rmin + wave) * cols + cmin + lane;  // record index in the staging view
+            if (lane < fw) {
+#pragma unroll
+                for (int j = 0; j < kStageSlots; ++j)
+                    if (wave + 4 * j < fh) pre[j] = src.load(vw, g + 4 * j * cols);
+            }
         }
     };
     auto staged = [](uint2 f) { return f.y != kFootprintSkip && f.y != kFootprintDirect; };
-    auto stage = [&](Rec* buf, uint2 f) {  // the prefetched records into LDS
+    auto stage = [&](StageT* buf, uint2 f) {  // the prefetched records or pixels into LDS
         const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
-        if (lane < fw) {
-            Rec* dst = buf + wave * fw + lane;
+        if constexpr (kRaw) {
+            if (lane <= fw) {
+                StageT* dst = buf + wave * kRawStride + lane;
 #pragma unroll
-            for (int j = 0; j < kStageSlots; ++j)
-                if (wave + 4 * j < fh) dst[4 * j * fw] = pre[j];
+                for (int j = 0; j < kStageSlots; ++j)
+                    if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = pre[j];
+            }
+        } else {
+            if (lane < fw) {
+                StageT* dst = buf + wave * fw + lane;
+#pragma unroll
+                for (int j = 0; j < kStageSlots; ++j)
+                    if (wave + 4 * j < fh) dst[4 * j * fw] = pre[j];
+            }
+        }
+    };
+    // Patch (r0, c0) of the staged footprint, as a record.  Records: row stride fw; pixels: the
+    // four corners at a fixed row stride.  `off` is the byte offset of (r0, c0) in the stage.
+    auto staged_rec = [&](uint32_t off) -> Rec {
+        const char* lds_b = reinterpret_cast<const char*>(lds);
+        if constexpr (kRaw) {
+            const float* q = static_cast<const float*>(__builtin_assume_aligned(lds_b + off, 4));
+            return RawPatchSource::record(q[0], q[1], q[kRawStride], q[kRawStride + 1]);
+        } else {
+            return *static_cast<const Rec*>(__builtin_assume_aligned(lds_b + off, sizeof(Rec)));
         }
     };
     uint2 f_next = fp_row[0];
@@ -598,7 +688,12 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
         const float s_lo = (float)cmin, s_hi = (float)(cmin + fw - 1);
         const float t_lo = (float)rmin, t_hi = (float)(rmin + fh - 1);
-        const int base = -(rmin * fw + cmin);
+        // byte offsets of the stage, so that a row's address is one 24-bit multiply-add:
+        // patch (r0, c0) at r0 * row_b + (c0 - cmin - rmin * stride) * elem
+        const int stride = kRaw ? kRawStride : fw;
+        const uint32_t elem = (uint32_t)sizeof(StageT);
+        const uint32_t row_b = (uint32_t)stride * elem;
+        const int base = -(rmin * stride + cmin);
         if (c.mode == kModeColumn) {
             const float r = __builtin_amdgcn_rcpf(wxy);
             const float sc = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), s_lo, s_hi);
@@ -607,18 +702,14 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             const float r2 = src.weight_column(view, r);
             const float dt = c.p[6] * r;
             const float tb = fmaf(vxy, r, 1.0f);
-            // byte offsets, so that the row's address is one 24-bit multiply-add
-            const uint32_t row_b = (uint32_t)fw * (uint32_t)sizeof(Rec);
-            const uint32_t cb_b = (uint32_t)(base + c0) * (uint32_t)sizeof(Rec);
-            const char* lds_b = reinterpret_cast<const char*>(lds);
+            const uint32_t cb_b = (uint32_t)(base + c0) * elem;
 #pragma unroll
             for (int i = 0; i < ZU; ++i) {
                 const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), t_lo, t_hi);
                 const int r0 = (int)t;
                 const float fy = __builtin_amdgcn_fractf(t);
-                const Rec* q = static_cast<const Rec*>(
-                    __builtin_assume_aligned(lds_b + (__umul24((uint32_t)r0, row_b) + cb_b), sizeof(Rec)));
-                acc[i] = fmaf(Src::eval(*q, fx, fy), r2, acc[i]);
+                const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + cb_b);
+                acc[i] = fmaf(Src::eval(q, fx, fy), r2, acc[i]);
             }
         } else {  // safe
 #pragma unroll
@@ -628,8 +719,8 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
                 const float sv = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), s_lo, s_hi);
                 const float tv = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), t_lo, t_hi);
                 const int c0 = (int)sv, r0 = (int)tv;
-                const float val = Src::eval(lds[__mul24(r0, fw) + c0 + base], __builtin_amdgcn_fractf(sv),
-                                            __builtin_amdgcn_fractf(tv));
+                const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + (uint32_t)(base + c0) * elem);
+                const float val = Src::eval(q, __builtin_amdgcn_fractf(sv), __builtin_amdgcn_fractf(tv));
                 acc[i] += val * src.weight_voxel(view, r);
             }
         }
@@ -658,15 +749,15 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // than the FP32 rounding of the pass, and is cut to the bordered frame
 // [0, W+1] x [0, H+1].  Entry {0, kFootprintSkip}: the tile projects off the
 // detector (the test of cull_kernel, exact zeros); {0, kFootprintDirect}: a
-// guarded view, a footprint wider than 64 records, taller than
-// kStageMaxHeight or of more than `cap` records, or one of the views k with
+// guarded view, a footprint wider than max_w records, taller than max_h or
+// of more than `cap` records, or one of the views k with
 // k % 8 < direct_eighths -- those read their taps directly, so that the
 // pass draws on the L1 path and the LDS path at once.  One thread per
 // (tile, view).
 // ---------------------------------------------------------------------------
 __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
-                                 int gx, int gy, int n_tiles, int W, int H, int cap, int direct_eighths,
-                                 uint2* __restrict__ out)
+                                 int gx, int gy, int n_tiles, int W, int H, int cap, int max_w, int max_h,
+                                 int direct_eighths, uint2* __restrict__ out)
 {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long)n_tiles * n_views) return;
@@ -713,7 +804,7 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     const int r0 = (int)fmin(fmax(floor(tmin) - 1.0, 0.0), (double)(H + 1));
     const int r1 = (int)fmin(fmax(floor(tmax) + 2.0, 0.0), (double)(H + 1));
     const int fw = max(c1 - c0 + 1, 1), fh = max(r1 - r0 + 1, 1);
-    if (fw > kStageMaxWidth || fh > kStageMaxHeight || (long)fw * fh > cap) {
+    if (fw > max_w || fh > max_h || (long)fw * fh > cap) {
         out[id] = make_uint2(0u, kFootprintDirect);
         return;
     }
@@ -1001,7 +1092,7 @@ hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_u
 }
 
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            int cap, int direct_eighths, uint2* out, hipStream_t s)
+                            bool raw, int direct_eighths, uint2* out, hipStream_t s)
 {
     const int tx = tile_x, ty = kBlock / tile_x;
     const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
@@ -1009,7 +1100,9 @@ hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_un
     const long total = tiles * n;
     const int threads = 256;
     hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
-                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, cap, direct_eighths, out);
+                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, raw ? kRawStride * kRawRows : kStageRecords,
+                       raw ? kStageMaxWidth - 1 : kStageMaxWidth, raw ? kStageMaxHeight - 1 : kStageMaxHeight,
+                       direct_eighths, out);
     return hipGetLastError();
 }
 
@@ -1041,9 +1134,25 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 
 hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
-                              int xcd_order, const float* inv_scale, const uint2* fp, hipStream_t s)
+                              int xcd_order, const float* inv_scale, const uint2* fp, const float* raw,
+                              hipStream_t s)
 {
     const uint8_t* base = (const uint8_t*)src;
+    if (fp && raw && layout == Layout::Patch) {
+        RawPatchSource ps;
+        ps.base = base;
+        ps.W = W;
+        ps.H = H;
+        ps.raw = raw;
+        switch (tile_x) {
+        case 64: return launch_zu_lds<RawPatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 32: return launch_zu_lds<RawPatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 16: return launch_zu_lds<RawPatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 8: return launch_zu_lds<RawPatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (raw) return hipErrorInvalidValue;  // pixels are staged for FP32 records only
     if (fp && layout == Layout::Patch16) {
         const Patch16Source ps{base, W, H, inv_scale};
         switch (tile_x) {

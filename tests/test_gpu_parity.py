@@ -297,7 +297,7 @@ def test_parity_l512_sampled(dtype, compact):
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
               order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1,
-              staging="auto"):
+              staging="auto", stage_records=False):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -306,7 +306,8 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
-                        direct_taps=direct_taps, wide_staging=wide_staging, staging=staging)
+                        direct_taps=direct_taps, wide_staging=wide_staging, staging=staging,
+                        stage_records=stage_records)
         ctx.set_tap_split(tap_split)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
@@ -377,8 +378,9 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
 @pytest.mark.parametrize("dtype,wide", [("f32", False), ("f16", False), ("bf16", False), ("bf16", True)])
 def test_lds_staged_taps_are_bit_identical(dtype, wide):
     """Taps staged through LDS per (tile, view) footprint give the same bits as direct taps, for any
-    share of views read directly: column and general branches, culled tiles, guarded views (direct
-    inside the staged pass), and footprints too large for LDS (direct as well)."""
+    share of views read directly and with FP32 footprints staged as pixels or as records: column and
+    general branches, culled tiles, guarded views (direct inside the staged pass), footprints too
+    large for LDS (direct as well), and footprints at the detector's edges (zero pixels)."""
     sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)
     proj = synth.filtered_projections(sc, synth.random_ellipsoids(77))
     if dtype != "f32":
@@ -396,6 +398,10 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
                 b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
                               tap_split=split, **kw)
                 assert np.array_equal(a, b), (shape, vs, kw, tx, zu, split)
+            if dtype == "f32":  # FP32 footprints staged as records instead of pixels
+                b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, tap_split=0,
+                              stage_records=True, **kw)
+                assert np.array_equal(a, b), (shape, vs, kw, tx, zu, "records")
             assert np.abs(a).max() > 0
 
 

@@ -206,8 +206,10 @@ bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use; any output may be NULL.
  * direct_taps: 1 if the fused pass reads every tap through L1 (no LDS stage) -- set by
- * BP_OPT_DIRECT_TAPS, or chosen for FP32 records on boxes of 2e8 voxels or more unless a tap
- * split is set. */
+ * BP_OPT_DIRECT_TAPS, or chosen on boxes of 2e8 voxels or more for FP32 projections staged as
+ * records (BP_OPT_STAGE_RECORDS, or 16-bit input with BP_OPT_WIDE_STAGING) unless a tap split
+ * is set.  FP32 projections staged as pixels (the default) keep the stage, with K = 128 on
+ * boxes of 2e8 voxels or more. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
                         bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x, int *direct_taps);
 

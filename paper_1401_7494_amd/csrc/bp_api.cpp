@@ -208,19 +208,23 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
         p.path = voxels < 8.0 * ctx->cfg.det_width * (double)ctx->cfg.det_height ? BP_PATH_FUSED_DIRECT
                                                                                   : BP_PATH_FUSED;
     }
-    // Staged or direct taps for the fused pass.  FP32 records of a fine grid (many voxels per
-    // detector pixel) reuse the L1 well enough that the direct loads win: measured at 1248 x 960
-    // pixels and a 256 mm field of view, the staged-and-direct split is ahead at L = 512 and
-    // behind from L = 640 up; compact records favour the split at every size.
+    // Staged or direct taps for the fused pass.  FP32 records staged as records, on a fine grid
+    // (many voxels per detector pixel), reuse the L1 well enough that the direct loads win:
+    // measured at 1248 x 960 pixels and a 256 mm field of view, that split is ahead at L = 512
+    // and behind from L = 640 up.  Compact records, and FP32 footprints staged as pixels, favour
+    // the split at every size measured (pixels at L = 1024: 2675 GUPS against 2396 direct).
     const bool compact = ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING);
+    const bool pixels = ctx->cfg.proj_dtype == BP_F32 && !(ctx->options & BP_OPT_STAGE_RECORDS);
     const double voxels = (double)nx * (double)ny * (double)nz;
     p.direct_taps = p.path == BP_PATH_FUSED &&
-                    ((ctx->options & BP_OPT_DIRECT_TAPS) || (!compact && ctx->tap_split < 0 && voxels >= 2.0e8));
+                    ((ctx->options & BP_OPT_DIRECT_TAPS) ||
+                     (!compact && !pixels && ctx->tap_split < 0 && voxels >= 2.0e8));
     p.k = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
     if (p.k <= 0) {
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
         else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
-        else p.k = compact ? 128 : 64;  // LDS-staged taps (measured at L = 512, 496 views)
+        // LDS-staged taps, measured at 496 views: K = 64 at L = 512, 128 at L = 1024 (+4%)
+        else p.k = compact || (pixels && voxels >= 2.0e8) ? 128 : 64;
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;

@@ -180,7 +180,7 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_set_tuning(h, 9, 0, 0, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 3, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_options(h, 1 << 12) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 1 << 13) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_options(h, 3 << 5) == bp.BP_ERR_INVALID_ARG  # region split of 3 along x
         assert L.bp_set_options(h, (1 << 10) | (1 << 11)) == bp.BP_ERR_INVALID_ARG  # serial and overlapped
         torch.cuda.synchronize()
@@ -213,10 +213,14 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
-        # staged or direct taps: FP32 records stage at L = 512, read directly on finer, larger grids
+        # staged or direct taps: FP32 pixel stages at every size (K = 128 on large grids); FP32
+        # record stages at L = 512, direct reads on finer, larger grids
         ctx.set_tuning("auto", 0, 0, 0)
         p = ctx.plan(512, 512, 512, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, False)
+        p = ctx.plan(1024, 1024, 1024, 496)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
+        ctx.set_options(stage_records=True)
         p = ctx.plan(640, 640, 640, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, True)
         ctx.set_tap_split(4)  # an explicit split keeps the stage

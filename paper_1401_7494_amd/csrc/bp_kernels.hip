@@ -46,8 +46,9 @@ constexpr int kXcds = 8;     // MI355X: 8 XCDs, consecutive workgroups go to con
 constexpr int kStageSlots = 8;
 constexpr int kStageMaxWidth = 64, kStageMaxHeight = 4 * kStageSlots;
 // FP32 pixels staged for the footprint of fw x fh patches: (fw + 1) x (fh + 1) pixels, at most 64 x 32,
-// in rows of a fixed stride so that a patch's four pixels are two ds_read2_b32 with immediate offsets.
-constexpr int kRawStride = kStageMaxWidth + 1, kRawRows = kStageMaxHeight;
+// in rows of a fixed stride so that a patch's four pixels are two ds_read2_b32 with immediate offsets
+// (four floats past the 64 pixels: fewer LDS bank conflicts than 65, measured).
+constexpr int kRawStride = kStageMaxWidth + 4, kRawRows = kStageMaxHeight;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {

@@ -259,7 +259,8 @@ struct RawPatchSource : PatchSource {
     const float* raw;  // the caller's images of the pass, [n][H][W]
     static constexpr bool kRawStage = true;
 
-    // View k's pixels as a byte-addressed buffer of W H FP32 values: offsets past the end read 0.
+    // View k's pixels as a byte-addressed buffer of W H FP32 values: offsets past the end read 0
+    // (the buffer's range check; no memory access).
     __device__ __forceinline__ i32x4_t raw_view(int k) const
     {
         const uint64_t a = (uint64_t)(raw + (size_t)k * W * H);
@@ -593,19 +594,24 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
-            // padded pixel (r, c) is detector pixel (c - 1, r - 1): byte offset ((r - 1) W + c - 1) 4,
-            // in 32-bit arithmetic, so rows above the detector wrap past the end and read 0 as rows
-            // below it do; columns off the detector are sent past the end (W H 4 < 2^31).
+            // Padded pixel (r, c) is detector pixel (c - 1, r - 1), at byte offset ((r - 1) W + c - 1) 4
+            // of the view.  A pixel off the detector is read at an offset past the view's W H 4 < 2^31
+            // bytes, which the buffer's range check returns as 0 without a memory access: columns off
+            // the detector at kFar and beyond, rows below it past the end by themselves, the row above
+            // it (slot 0 of wave 0 when rmin = 0) at kFar.  No offset wraps in 32 bits (W <= 2^20).
+            constexpr uint32_t kFar = 0xC0000000u;
             const int c = cmin + lane;
             const bool col_ok = (lane <= fw) & (c >= 1) & (c <= src.W);
             const uint32_t row_bytes = (uint32_t)src.W * 4u;
-            const uint32_t off0 = col_ok ? (uint32_t)(rmin - 1 + wave) * row_bytes + (uint32_t)(c - 1) * 4u
-                                         : 0x80000000u;
+            // slot 1's row, rmin + 3 + wave >= 3, is never above the detector
+            const uint32_t off1 = col_ok ? (uint32_t)(rmin + 3 + wave) * row_bytes + (uint32_t)(c - 1) * 4u : kFar;
             const i32x4_t rs = src.raw_view(k);
+            if (wave <= fh)
+                pre[0] = raw_buffer_load_f32(rs, (int)(rmin - 1 + wave >= 0 ? off1 - 4u * row_bytes : kFar), 0, 0);
 #pragma unroll
-            for (int j = 0; j < kStageSlots; ++j)
+            for (int j = 1; j < kStageSlots; ++j)
                 if (wave + 4 * j <= fh)
-                    pre[j] = raw_buffer_load_f32(rs, (int)(off0 + (uint32_t)(4 * j) * row_bytes), 0, 0);
+                    pre[j] = raw_buffer_load_f32(rs, (int)(off1 + (uint32_t)(4 * (j - 1)) * row_bytes), 0, 0);
         } else {
             const auto vw = src.view(k);
             const int cols = src.cols();

@@ -409,6 +409,27 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
             assert np.abs(a).max() > 0
 
 
+def test_pixel_stage_at_the_detector_corners():
+    """Boxes straddling the detector's corners (footprints that reach the bordered frame's first
+    and last rows and columns): FP32 pixels staged in LDS, with every pixel off the detector read
+    as 0, give the same bits as the records read directly, and match the oracle."""
+    sc = synth.Scanner(n_views=16, W=96, H=64, pitch=2.0)
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(79))
+    P32 = gc.product_matrices(sc)
+    shape, vs = (24, 40, 40), 2.0
+    for cx, cy, cz in ((60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
+        o = _box_origin(shape, vs)
+        origin = (o[0] + cx, o[1] + cy, o[2] + cz)
+        a = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, direct_taps=True)
+        for split in (0, -1):
+            b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, tap_split=split)
+            assert np.array_equal(a, b), ((cx, cy, cz), split)
+        assert np.abs(a).max() > 0
+    ref = _oracle_box(proj.numpy(), P32, shape, vs, origin)
+    err = gc.error_stats(b, ref)
+    assert err["rel_l2"] <= gc.REL_L2_TOL, err
+
+
 @pytest.mark.parametrize("dtype,wide", [("f32", False), ("bf16", False), ("bf16", True)])
 def test_staging_overlap_is_bit_identical(dtype, wide):
     """Staging the next pass on the context's side stream while the current pass runs gives the same

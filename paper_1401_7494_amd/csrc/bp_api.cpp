@@ -475,7 +475,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     if (staged) {
         st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, pad_half * halves, "staged projections");
         if (st != BP_OK) return st;
-        if (layout == bp::Layout::Patch16) {
+        if (layout == bp::Layout::Patch16 || raw_stage) {
             st = ensure(ctx, &ctx->d_scale, &ctx->scale_cap, scale_half * halves, "staging scales");
             if (st != BP_OK) return st;
         }
@@ -530,20 +530,30 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             // this half was last read by the pass two before
             if (overlap && pass >= 2 && hipStreamWaitEvent(ss, ctx->ev_done[half], 0) != hipSuccess)
                 return fail(ctx, BP_ERR_LAUNCH, "cannot order the staging stream");
-            e = timed(ctx, 1, ss, [&] {
-                return layout == bp::Layout::Patch16
-                           ? bp::launch_patch16(dt, src_views, W, H, kc, pad, maxabs, inv_scale, ss)
-                           : bp::launch_patch(dt, src_views, W, H, kc, pad, ss);
-            });
-            if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
+            // Footprints first: with pixel stages they flag the views whose records are read at all
+            // (the scale scratch holds the pass's flags), and only those are staged as records.
+            bp::ViewNeed need;
+            if (raw_stage) {
+                need.vc = ctx->d_views + k0;
+                need.big = maxabs;
+                need.direct_eighths = split;
+                e = timed(ctx, 2, ss, [&] { return bp::launch_zero(maxabs, kc, ss); });
+                if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("fill kernel: ") + hipGetErrorString(e));
+            }
             if (lds) {
                 e = timed(ctx, 2, ss, [&] {
                     return bp::launch_footprint(ctx->d_views + k0, kc, box, plan.zu, plan.tx, W, H, raw_stage,
-                                                split, fp, ss);
+                                                split, fp, raw_stage ? maxabs : nullptr, ss);
                 });
                 if (e != hipSuccess)
                     return fail(ctx, BP_ERR_LAUNCH, std::string("footprint kernel: ") + hipGetErrorString(e));
             }
+            e = timed(ctx, 1, ss, [&] {
+                return layout == bp::Layout::Patch16
+                           ? bp::launch_patch16(dt, src_views, W, H, kc, pad, maxabs, inv_scale, ss)
+                           : bp::launch_patch(dt, src_views, W, H, kc, pad, need, ss);
+            });
+            if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("staging kernel: ") + hipGetErrorString(e));
             if (overlap && (hipEventRecord(ctx->ev_staged[half], ss) != hipSuccess ||
                             hipStreamWaitEvent(s, ctx->ev_staged[half], 0) != hipSuccess))
                 return fail(ctx, BP_ERR_LAUNCH, "cannot order the pass after its staging");

@@ -57,7 +57,21 @@ hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, boo
                              hipStream_t s);
 
 // Bilinear-patch staging copy of views [0, n) of `proj`.
-hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, hipStream_t s);
+// Which views of a pass need their patch records when the staged footprints hold
+// pixels: the views the tap split sends to L1 (k % 8 < direct_eighths), guarded
+// views (vc[k].mode), and views with a footprint too large for the stage
+// (big[k] != 0, set by launch_footprint).  vc == null: every view.
+struct ViewNeed {
+    const ViewConst* vc = nullptr;
+    const uint32_t* big = nullptr;
+    int direct_eighths = 8;
+};
+
+hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, const ViewNeed& need,
+                        hipStream_t s);
+
+// Fill n words with 0 (a kernel, so that a captured graph holds no memset node).
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
 
 // Compact (FP16, scaled) bilinear-patch staging of views [0, n): per-view
 // max |pixel| into maxabs[n] (scratch), 2^-e scale into inv_scale[n].
@@ -90,10 +104,12 @@ constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
 
 // Footprint table of one pass: n views (view constants vc[0, n)), every tile;
 // views with k % 8 < direct_eighths are marked to read their taps directly.
-// raw: footprints sized for staging FP32 pixels (fw < 64, fh < 32) rather
+// raw: footprints sized for staging FP32 pixels (fw < 64, fh < 36) rather
 // than patch records (fw <= 64, fh <= 32, fw fh <= kStageRecords).
+// big (may be null): big[k] = 1 for a view with a footprint too large for the
+// stage, whose records are then read directly (big zeroed beforehand).
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            bool raw, int direct_eighths, uint2* out, hipStream_t s);
+                            bool raw, int direct_eighths, uint2* out, uint32_t* big, hipStream_t s);
 
 // Tiles of a pass: tile_x x (256 / tile_x) x z_unroll voxels each.
 inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)

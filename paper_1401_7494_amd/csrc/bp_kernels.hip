@@ -48,7 +48,9 @@ constexpr int kStageMaxWidth = 64, kStageMaxHeight = 4 * kStageSlots;
 // FP32 pixels staged for the footprint of fw x fh patches: (fw + 1) x (fh + 1) pixels, at most 64 x 32,
 // in rows of a fixed stride so that a patch's four pixels are two ds_read2_b32 with immediate offsets
 // (four floats past the 64 pixels: fewer LDS bank conflicts than 65, measured).
-constexpr int kRawStride = kStageMaxWidth + 4, kRawRows = kStageMaxHeight;
+constexpr int kRawStride = kStageMaxWidth + 4;
+// Slots of a pixel stage: 36 rows, so that footprints of the benchmark geometry never exceed them.
+constexpr int kRawSlots = kStageSlots + 1, kRawRows = 4 * kRawSlots;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {
@@ -586,8 +588,9 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     // The next staged footprint, loaded while the current view is computed: footprint row
     // wave + 4 j is slot j of that wave, one column per lane.  Records: fw <= 64 and fh <= 4
     // kStageSlots; FP32 pixels: the fw + 1 columns and fh + 1 rows of the patches' corners,
-    // fw < 64 and fh < 4 kStageSlots (the footprint table keeps to these bounds).
-    StageT pre[kStageSlots];
+    // fw < 64 and fh < 4 kRawSlots (the footprint table keeps to these bounds).
+    constexpr int kSlots = kRaw ? kRawSlots : kStageSlots;
+    StageT pre[kSlots];
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
     auto prefetch = [&](int k, uint2 f) {
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             if (wave <= fh)
                 pre[0] = raw_buffer_load_f32(rs, (int)(rmin - 1 + wave >= 0 ? off1 - 4u * row_bytes : kFar), 0, 0);
 #pragma unroll
-            for (int j = 1; j < kStageSlots; ++j)
+            for (int j = 1; j < kSlots; ++j)
                 if (wave + 4 * j <= fh)
                     pre[j] = raw_buffer_load_f32(rs, (int)(off1 + (uint32_t)(4 * (j - 1)) * row_bytes), 0, 0);
         } else {
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             const int g = (rmin + wave) * cols + cmin + lane;  // record index in the staging view
             if (lane < fw) {
 #pragma unroll
-                for (int j = 0; j < kStageSlots; ++j)
+                for (int j = 0; j < kSlots; ++j)
                     if (wave + 4 * j < fh) pre[j] = src.load(vw, g + 4 * j * cols);
             }
         }
@@ -630,14 +633,14 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             if (lane <= fw) {
                 StageT* dst = buf + wave * kRawStride + lane;
 #pragma unroll
-                for (int j = 0; j < kStageSlots; ++j)
+                for (int j = 0; j < kSlots; ++j)
                     if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = pre[j];
             }
         } else {
             if (lane < fw) {
                 StageT* dst = buf + wave * fw + lane;
 #pragma unroll
-                for (int j = 0; j < kStageSlots; ++j)
+                for (int j = 0; j < kSlots; ++j)
                     if (wave + 4 * j < fh) dst[4 * j * fw] = pre[j];
             }
         }
@@ -693,8 +696,11 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         }
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
-        const float s_lo = (float)cmin, s_hi = (float)(cmin + fw - 1);
-        const float t_lo = (float)rmin, t_hi = (float)(rmin + fh - 1);
+        // positions are clamped into [cmin, cmin + fw) x [rmin, rmin + fh) (the upper bounds the
+        // largest floats below them): a position inside keeps its fraction, and the patch stays in
+        // the footprint
+        const float s_lo = (float)cmin, s_hi = __int_as_float(__float_as_int((float)(cmin + fw)) - 1);
+        const float t_lo = (float)rmin, t_hi = __int_as_float(__float_as_int((float)(rmin + fh)) - 1);
         // byte offsets of the stage, so that a row's address is one 24-bit multiply-add:
         // patch (r0, c0) at r0 * row_b + (c0 - cmin - rmin * stride) * elem
         const int stride = kRaw ? kRawStride : fw;
@@ -752,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // can read.  The corners' positions (FP64, padded coordinates s = u/w + 1,
 // t = v/w + 1) bound every voxel's position (w > 0 on the box, so the image
 // of the tile is the convex hull of the corners' images); the rectangle adds
-// one record below and two above the corners' range on each axis, far more
+// one record below and one above the corners' range on each axis, far more
 // than the FP32 rounding of the pass, and is cut to the bordered frame
 // [0, W+1] x [0, H+1].  Entry {0, kFootprintSkip}: the tile projects off the
 // detector (the test of cull_kernel, exact zeros); {0, kFootprintDirect}: a
@@ -764,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // ---------------------------------------------------------------------------
 __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
                                  int gx, int gy, int n_tiles, int W, int H, int cap, int max_w, int max_h,
-                                 int direct_eighths, uint2* __restrict__ out)
+                                 int direct_eighths, uint2* __restrict__ out, uint32_t* __restrict__ big)
 {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long)n_tiles * n_views) return;
@@ -807,12 +813,13 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     }
     // fmin / fmax also map a NaN to the frame
     const int c0 = (int)fmin(fmax(floor(smin) - 1.0, 0.0), (double)(W + 1));
-    const int c1 = (int)fmin(fmax(floor(smax) + 2.0, 0.0), (double)(W + 1));
+    const int c1 = (int)fmin(fmax(floor(smax) + 1.0, 0.0), (double)(W + 1));
     const int r0 = (int)fmin(fmax(floor(tmin) - 1.0, 0.0), (double)(H + 1));
-    const int r1 = (int)fmin(fmax(floor(tmax) + 2.0, 0.0), (double)(H + 1));
+    const int r1 = (int)fmin(fmax(floor(tmax) + 1.0, 0.0), (double)(H + 1));
     const int fw = max(c1 - c0 + 1, 1), fh = max(r1 - r0 + 1, 1);
     if (fw > max_w || fh > max_h || (long)fw * fh > cap) {
         out[id] = make_uint2(0u, kFootprintDirect);
+        if (big) big[k] = 1u;  // this view's records are read after all (every writer stores 1)
         return;
     }
     out[id] = make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16), (uint32_t)fw | ((uint32_t)fh << 16));
@@ -923,12 +930,14 @@ __device__ __forceinline__ float pixel_f32(const T* img, int W, int H, int i, in
 // Bilinear-patch staging copy: one thread per patch (r, c) of a (H+2) x (W+2) grid.
 template <typename T>
 __global__ __launch_bounds__(256) void patch_kernel(const T* __restrict__ proj, int W, int H,
-                                                    f32x4_t* __restrict__ out)
+                                                    f32x4_t* __restrict__ out, ViewNeed need)
 {
     const int Wq = W + 2, Hq = H + 2;
     const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int r = (int)blockIdx.y;
     const int k = (int)blockIdx.z;
+    if (need.vc && (k & 7) >= need.direct_eighths && need.vc[k].mode != kModeGuarded && need.big[k] == 0u)
+        return;  // whole block: no tile reads this view's records
     if (c >= Wq || r >= Hq) return;
     const T* img = proj + (size_t)k * W * H;
     const int i = c - 1, j = r - 1;  // detector pixel of the patch's first corner
@@ -1071,16 +1080,29 @@ hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, boo
     return hipGetLastError();
 }
 
-hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, hipStream_t s)
+hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* out, const ViewNeed& need,
+                        hipStream_t s)
 {
     const dim3 block(256, 1, 1);
     const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)(H + 2), (unsigned)n);
     f32x4_t* q = (f32x4_t*)out;
     switch (dt) {
-    case Dtype::F32: hipLaunchKernelGGL(patch_kernel<float>, grid, block, 0, s, (const float*)proj, W, H, q); break;
-    case Dtype::F16: hipLaunchKernelGGL(patch_kernel<__half>, grid, block, 0, s, (const __half*)proj, W, H, q); break;
-    case Dtype::BF16: hipLaunchKernelGGL(patch_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)proj, W, H, q); break;
+    case Dtype::F32:
+        hipLaunchKernelGGL(patch_kernel<float>, grid, block, 0, s, (const float*)proj, W, H, q, need);
+        break;
+    case Dtype::F16:
+        hipLaunchKernelGGL(patch_kernel<__half>, grid, block, 0, s, (const __half*)proj, W, H, q, need);
+        break;
+    case Dtype::BF16:
+        hipLaunchKernelGGL(patch_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)proj, W, H, q, need);
+        break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -1099,7 +1121,7 @@ hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_u
 }
 
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
-                            bool raw, int direct_eighths, uint2* out, hipStream_t s)
+                            bool raw, int direct_eighths, uint2* out, uint32_t* big, hipStream_t s)
 {
     const int tx = tile_x, ty = kBlock / tile_x;
     const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
@@ -1108,8 +1130,8 @@ hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_un
     const int threads = 256;
     hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
                        n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, raw ? kRawStride * kRawRows : kStageRecords,
-                       raw ? kStageMaxWidth - 1 : kStageMaxWidth, raw ? kStageMaxHeight - 1 : kStageMaxHeight,
-                       direct_eighths, out);
+                       raw ? kStageMaxWidth - 1 : kStageMaxWidth, raw ? kRawRows - 1 : kStageMaxHeight,
+                       direct_eighths, out, big);
     return hipGetLastError();
 }
 

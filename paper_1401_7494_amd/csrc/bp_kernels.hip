@@ -534,16 +534,19 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// The fused pass with the taps staged through LDS.  For each view of the pass
-// the block first copies its tile's footprint -- the rectangle of patch
-// records that any voxel of the tile can read, from the footprint table --
-// from the staging buffer into LDS with coalesced row loads, then every
-// voxel reads its one patch record from LDS.  The positions are clamped to
-// the footprint instead of the bordered frame; the footprint holds every
-// position the tile's voxels reach with a margin (see footprint_kernel), so
-// the clamp only ever acts at the detector border, exactly as in the direct
-// pass, and the results are bit-identical to it.  Views whose footprint does
-// not fit the LDS buffer, and guarded views, read their taps directly.
+// The fused pass with the taps staged through LDS.  For each staged view of
+// the pass the block first copies its tile's footprint -- the rectangle of
+// patches that any voxel of the tile can read, from the footprint table --
+// into LDS with coalesced row loads: the patch records themselves (records
+// sources), or the caller's FP32 pixels at the patches' corners (pixel
+// sources), from which each update forms its patch with the record's own
+// FP32 operations.  Every voxel then reads its patch from LDS.  The positions
+// are clamped to the footprint instead of the bordered frame; the footprint
+// holds every position the tile's voxels reach with a margin (see
+// footprint_kernel), so the clamp only ever acts at the detector border,
+// exactly as in the direct pass, and the results are bit-identical to it.
+// The tap split's direct views, views whose footprint does not fit the
+// stage, and guarded views read their patch records directly.
 // ---------------------------------------------------------------------------
 template <class Src, bool RAW = Src::kRawStage>
 struct StageOf {

@@ -159,8 +159,8 @@ def time_form(bp, torch, form, proj_by_dtype, P, vol_cfg, steps, warmup, k, zu, 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the z-slab sharding across GPUs "
-              "is a design in DESIGN.md, not part of this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (sharding the volume into z-slabs "
+              "across GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

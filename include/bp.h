@@ -63,7 +63,7 @@ typedef struct bp_ctx_s *bp_ctx;
 typedef enum {
     BP_OK = 0,
     BP_ERR_INVALID_ARG = 1,   /* null pointer, bad size, non-finite geometry, ... */
-    BP_ERR_UNSUPPORTED = 2,   /* valid request this build cannot serve */
+    BP_ERR_UNSUPPORTED = 2,   /* valid request the library cannot serve */
     BP_ERR_OUT_OF_MEMORY = 3, /* device scratch could not be allocated */
     BP_ERR_DEVICE = 4,        /* HIP runtime error outside a launch */
     BP_ERR_LAUNCH = 5         /* a kernel launch was rejected */

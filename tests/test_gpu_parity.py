@@ -420,11 +420,14 @@ def test_pixel_stage_at_the_detector_corners():
     for cx, cy, cz in ((60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
         o = _box_origin(shape, vs)
         origin = (o[0] + cx, o[1] + cy, o[2] + cz)
+        for tx, zu in ((16, 8), (8, 4), (64, 1)):
+            a = _run_opts(proj, P32, shape, vs, origin, k=16, zu=zu, tx=tx, direct_taps=True)
+            for split in (0, -1):
+                b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=zu, tx=tx, tap_split=split)
+                assert np.array_equal(a, b), ((cx, cy, cz), tx, zu, split)
+            assert np.abs(a).max() > 0
         a = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, direct_taps=True)
-        for split in (0, -1):
-            b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, tap_split=split)
-            assert np.array_equal(a, b), ((cx, cy, cz), split)
-        assert np.abs(a).max() > 0
+        b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, tap_split=0)
     ref = _oracle_box(proj.numpy(), P32, shape, vs, origin)
     err = gc.error_stats(b, ref)
     assert err["rel_l2"] <= gc.REL_L2_TOL, err

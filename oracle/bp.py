@@ -45,6 +45,10 @@ def _bind(lib):
         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
         ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
     ]
+    lib.oracle_backproject_abs.restype = ctypes.c_int
+    lib.oracle_backproject_abs.argtypes = lib.oracle_backproject.argtypes
+    lib.oracle_backproject_points_abs.restype = ctypes.c_int
+    lib.oracle_backproject_points_abs.argtypes = lib.oracle_backproject_points.argtypes
     lib.oracle_interpolate.restype = ctypes.c_double
     lib.oracle_interpolate.argtypes = [
         ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -75,7 +79,7 @@ def default_threads() -> int:
     return max(1, n)
 
 
-def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=None, lib=None):
+def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=None, lib=None, absolute=False):
     """Back project ``proj`` into (a block of) an L^3 volume, in FP64.
 
     proj        (N, H, W) array; widened exactly to FP32 storage (the values the
@@ -87,6 +91,8 @@ def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=No
     block       ((x0, x1), (y0, y1), (z0, z1)) half-open voxel ranges; whole
                 volume if None.
     vol         optional FP64 array (nz, ny, nx) to accumulate into.
+    absolute    sum |contribution| of every view instead (the magnitude of the
+                summands, which sets the sum's conditioning).
     Returns the FP64 block, indexed [z, y, x].
     """
     lib = lib or load_library()
@@ -106,7 +112,8 @@ def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=No
         if vol.shape != (nz, ny, nx):
             raise ValueError("vol has the wrong shape")
     o = np.ascontiguousarray(np.asarray(origin, dtype=np.float64).reshape(3))
-    rc = lib.oracle_backproject(
+    fn = lib.oracle_backproject_abs if absolute else lib.oracle_backproject
+    rc = fn(
         vol.ctypes.data, x0, y0, z0, nx, ny, nz,
         proj.ctypes.data, W, H, n,
         P.ctypes.data, float(voxel_size), o.ctypes.data,
@@ -117,8 +124,9 @@ def backproject(proj, P, L, voxel_size, origin, block=None, vol=None, threads=No
     return vol
 
 
-def backproject_points(proj, P, voxel_size, origin, xyz, threads=None, lib=None):
-    """FP64 back projection of a list of voxels ``xyz`` (M, 3) integer (x, y, z); returns (M,) FP64."""
+def backproject_points(proj, P, voxel_size, origin, xyz, threads=None, lib=None, absolute=False):
+    """FP64 back projection of a list of voxels ``xyz`` (M, 3) integer (x, y, z); returns (M,) FP64
+    (``absolute``: the sum of |contribution| instead)."""
     lib = lib or load_library()
     proj = np.ascontiguousarray(proj, dtype=np.float32)
     n, H, W = proj.shape
@@ -126,7 +134,8 @@ def backproject_points(proj, P, voxel_size, origin, xyz, threads=None, lib=None)
     xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1, 3)
     out = np.zeros(xyz.shape[0], dtype=np.float64)
     o = np.ascontiguousarray(np.asarray(origin, dtype=np.float64).reshape(3))
-    rc = lib.oracle_backproject_points(out.ctypes.data, xyz.ctypes.data, xyz.shape[0], proj.ctypes.data, W, H, n,
+    fn = lib.oracle_backproject_points_abs if absolute else lib.oracle_backproject_points
+    rc = fn(out.ctypes.data, xyz.ctypes.data, xyz.shape[0], proj.ctypes.data, W, H, n,
                                        P.ctypes.data, float(voxel_size), o.ctypes.data,
                                        int(threads if threads is not None else default_threads()))
     if rc != 0:

@@ -9,20 +9,21 @@
  *
  * What it computes -- voxel-driven cone-beam back projection as defined by the
  * RabbitCT reference module (Hofmann, Treibig, Hager, Wellein, WPMVP'14,
- * Sec. 4.1 "Algorithm", Listing 1), one projection image per view:
+ * Sec. 4.1 "Algorithm"), one projection image per view:
  *
- *   for every voxel (x, y, z) of the block and every view k = 0 .. N-1:
- *     Part 1 (geometry)
- *       (wx, wy, wz) = origin + MM * (x, y, z)        voxel centre, world coords
- *       (u, v, w)    = A_k * (wx, wy, wz, 1)          homogeneous detector coords
- *       ix = u / w,  iy = v / w                       de-homogenised position
- *     Part 2 (taps)
- *       iix = floor(ix), iiy = floor(iy)
- *       the four pixels (iix, iiy), (iix+1, iiy), (iix, iiy+1), (iix+1, iiy+1),
- *       each read as 0 when it lies off the detector
- *     Part 3 (interpolate, weight, accumulate)
- *       val = bilinear blend with scalex = ix - iix, scaley = iy - iiy
- *       VOL += val / (w * w)                          inverse-square weight
+ *   for every voxel of the block and every view k = 0 .. N-1:
+ *     X          = origin + MM * (x, y, z)            voxel centre, world coords
+ *     (u, v, w)  = P_k (X, 1)                         homogeneous detector coords
+ *     (s, t)     = (u / w, v / w)                     position on the detector
+ *     B_k(s, t)  = sum over pixels (i, j) of I_k[j][i] tent(s - i) tent(t - j),
+ *                  tent(r) = max(0, 1 - |r|), pixels off the detector 0
+ *                  (the bilinear interpolant of the zero-extended image; only
+ *                  the 2 x 2 pixels around (s, t) have a non-zero weight)
+ *     V[x, y, z] += B_k(s, t) / w^2                   inverse-square weight
+ *
+ * A second mode sums |B_k(s, t) / w^2| instead: the magnitude of what the
+ * back projection adds up, which sets how much any finite-precision
+ * evaluation of the sum can be off (the sum's conditioning).
  *
  * Readings where the printed listing is silent or slips (each is also listed
  * in the design notes of the repository):
@@ -34,9 +35,9 @@
  *   - the origin is given per axis (voxel (0,0,0) centre);
  *   - a view contributes 0 to a voxel unless w > 0 (voxel in front of the
  *     source);
- *   - positions with ix <= -1, ix >= W, iy <= -1 or iy >= H contribute 0
- *     exactly (all four taps are off the detector), which is tested before
- *     the float-to-integer conversion so huge coordinates cannot overflow it.
+ *   - positions with s <= -1, s >= W, t <= -1 or t >= H contribute 0
+ *     exactly (every pixel with a weight is off the detector), which is tested
+ *     before the float-to-integer conversion so huge positions cannot overflow it.
  *
  * Threads split the block into independent z-planes, the task decomposition
  * of the paper's Sec. 5; each voxel is owned by exactly one thread.
@@ -54,22 +55,30 @@ static double pixel(const float *img, int W, int H, long i, long j)
     return (double)img[j * (long)W + i];
 }
 
-/* bilinear interpolant of the zero-extended image at detector position (ix, iy) */
-static double interpolate(const float *img, int W, int H, double ix, double iy)
+/* hat function of unit half-width */
+static double tent(double r)
 {
-    if (!(ix > -1.0 && ix < (double)W && iy > -1.0 && iy < (double)H))
+    r = fabs(r);
+    return r < 1.0 ? 1.0 - r : 0.0;
+}
+
+/* Bilinear interpolant of the zero-extended image at detector position (s, t): each pixel
+ * weighted by tent(s - i) tent(t - j).  The weights vanish outside the 2 x 2 pixels
+ * i = floor(s), floor(s) + 1 and j = floor(t), floor(t) + 1, so only those are summed;
+ * positions with s <= -1, s >= W, t <= -1 or t >= H weigh only pixels off the detector and
+ * give 0 (tested first, so that huge positions never reach the integer conversion). */
+static double interpolate(const float *img, int W, int H, double s, double t)
+{
+    if (!(s > -1.0 && s < (double)W && t > -1.0 && t < (double)H))
         return 0.0;
-    double fx = floor(ix), fy = floor(iy);
-    long iix = (long)fx, iiy = (long)fy;
-    double scalex = ix - fx;
-    double scaley = iy - fy;
-    double valbl = pixel(img, W, H, iix, iiy);
-    double valbr = pixel(img, W, H, iix + 1, iiy);
-    double valtl = pixel(img, W, H, iix, iiy + 1);
-    double valtr = pixel(img, W, H, iix + 1, iiy + 1);
-    double valb = (1.0 - scalex) * valbl + scalex * valbr;
-    double valt = (1.0 - scalex) * valtl + scalex * valtr;
-    return (1.0 - scaley) * valb + scaley * valt;
+    const long c0 = (long)floor(s), r0 = (long)floor(t);
+    double sum = 0.0;
+    for (long j = r0; j <= r0 + 1; ++j) {
+        const double wt = tent(t - (double)j);
+        for (long i = c0; i <= c0 + 1; ++i)
+            sum += pixel(img, W, H, i, j) * tent(s - (double)i) * wt;
+    }
+    return sum;
 }
 
 /* contribution of view k to the voxel centred at world position (wx, wy, wz) */
@@ -81,9 +90,7 @@ static double contribution(const float *img, int W, int H, const double *A,
     double w = A[8] * wx + A[9] * wy + A[10] * wz + A[11];
     if (!(w > 0.0))
         return 0.0;
-    double ix = u / w;
-    double iy = v / w;
-    double val = interpolate(img, W, H, ix, iy);
+    double val = interpolate(img, W, H, u / w, v / w);
     return val / (w * w);
 }
 
@@ -95,6 +102,7 @@ typedef struct {
     const double *P;
     double MM;
     double O[3];
+    int absolute;  /* sum |contribution| instead of the contribution */
     int first_plane, plane_step;
 } job_t;
 
@@ -110,9 +118,11 @@ static void *run_planes(void *arg)
                 double wx = jb->O[0] + jb->MM * (double)(jb->x0 + ix);
                 double *voxel = &jb->vol[((long)iz * jb->ny + iy) * jb->nx + ix];
                 double sum = *voxel;
-                for (int k = 0; k < jb->n_views; ++k)
-                    sum += contribution(jb->proj + k * img_size, jb->W, jb->H,
-                                        jb->P + 12 * (long)k, wx, wy, wz);
+                for (int k = 0; k < jb->n_views; ++k) {
+                    const double c = contribution(jb->proj + k * img_size, jb->W, jb->H,
+                                                  jb->P + 12 * (long)k, wx, wy, wz);
+                    sum += jb->absolute ? fabs(c) : c;
+                }
                 *voxel = sum;
             }
         }
@@ -132,9 +142,9 @@ static void *run_planes(void *arg)
  *   n_threads  <= 0 picks the number of online CPUs.
  * Returns 0, or -1 for an invalid argument.
  */
-int oracle_backproject(double *vol, int x0, int y0, int z0, int nx, int ny, int nz,
-                       const float *proj, int W, int H, int n_views,
-                       const double *P, double MM, const double *O, int n_threads)
+static int backproject_block(double *vol, int x0, int y0, int z0, int nx, int ny, int nz,
+                             const float *proj, int W, int H, int n_views,
+                             const double *P, double MM, const double *O, int n_threads, int absolute)
 {
     if (!vol || !proj || !P || !O || nx < 0 || ny < 0 || nz < 0 || W < 1 || H < 1 ||
         n_views < 0)
@@ -161,6 +171,7 @@ int oracle_backproject(double *vol, int x0, int y0, int z0, int nx, int ny, int 
         jb->proj = proj; jb->W = W; jb->H = H; jb->n_views = n_views;
         jb->P = P; jb->MM = MM;
         jb->O[0] = O[0]; jb->O[1] = O[1]; jb->O[2] = O[2];
+        jb->absolute = absolute;
         jb->first_plane = t;
         jb->plane_step = n_threads;
     }
@@ -181,6 +192,21 @@ int oracle_backproject(double *vol, int x0, int y0, int z0, int nx, int ny, int 
     return 0;
 }
 
+int oracle_backproject(double *vol, int x0, int y0, int z0, int nx, int ny, int nz,
+                       const float *proj, int W, int H, int n_views,
+                       const double *P, double MM, const double *O, int n_threads)
+{
+    return backproject_block(vol, x0, y0, z0, nx, ny, nz, proj, W, H, n_views, P, MM, O, n_threads, 0);
+}
+
+/* As oracle_backproject, adding |contribution| of every view (the sum's magnitude). */
+int oracle_backproject_abs(double *vol, int x0, int y0, int z0, int nx, int ny, int nz,
+                           const float *proj, int W, int H, int n_views,
+                           const double *P, double MM, const double *O, int n_threads)
+{
+    return backproject_block(vol, x0, y0, z0, nx, ny, nz, proj, W, H, n_views, P, MM, O, n_threads, 1);
+}
+
 typedef struct {
     double *out;
     const int *xyz;
@@ -190,6 +216,7 @@ typedef struct {
     const double *P;
     double MM;
     double O[3];
+    int absolute;
     long first, step;
 } points_job_t;
 
@@ -202,8 +229,10 @@ static void *run_points(void *arg)
         double wy = jb->O[1] + jb->MM * (double)jb->xyz[3 * m + 1];
         double wz = jb->O[2] + jb->MM * (double)jb->xyz[3 * m + 2];
         double sum = jb->out[m];
-        for (int k = 0; k < jb->n_views; ++k)
-            sum += contribution(jb->proj + k * img_size, jb->W, jb->H, jb->P + 12 * (long)k, wx, wy, wz);
+        for (int k = 0; k < jb->n_views; ++k) {
+            const double c = contribution(jb->proj + k * img_size, jb->W, jb->H, jb->P + 12 * (long)k, wx, wy, wz);
+            sum += jb->absolute ? fabs(c) : c;
+        }
         jb->out[m] = sum;
     }
     return NULL;
@@ -214,8 +243,9 @@ static void *run_points(void *arg)
  * views for voxel (xyz[3m], xyz[3m+1], xyz[3m+2]).  Used to sample a large
  * volume uniformly.  Returns 0, or -1 for an invalid argument.
  */
-int oracle_backproject_points(double *out, const int *xyz, long n, const float *proj, int W, int H,
-                              int n_views, const double *P, double MM, const double *O, int n_threads)
+static int backproject_list(double *out, const int *xyz, long n, const float *proj, int W, int H,
+                            int n_views, const double *P, double MM, const double *O, int n_threads,
+                            int absolute)
 {
     if (!out || !xyz || !proj || !P || !O || n < 0 || W < 1 || H < 1 || n_views < 0)
         return -1;
@@ -238,6 +268,7 @@ int oracle_backproject_points(double *out, const int *xyz, long n, const float *
         jb->proj = proj; jb->W = W; jb->H = H; jb->n_views = n_views;
         jb->P = P; jb->MM = MM;
         jb->O[0] = O[0]; jb->O[1] = O[1]; jb->O[2] = O[2];
+        jb->absolute = absolute;
         jb->first = t; jb->step = n_threads;
     }
     int started = 0;
@@ -256,8 +287,21 @@ int oracle_backproject_points(double *out, const int *xyz, long n, const float *
     return 0;
 }
 
-/* Bilinear interpolant of one zero-extended image at one position (exported for pins). */
-double oracle_interpolate(const float *img, int W, int H, double ix, double iy)
+int oracle_backproject_points(double *out, const int *xyz, long n, const float *proj, int W, int H,
+                              int n_views, const double *P, double MM, const double *O, int n_threads)
 {
-    return interpolate(img, W, H, ix, iy);
+    return backproject_list(out, xyz, n, proj, W, H, n_views, P, MM, O, n_threads, 0);
+}
+
+/* As oracle_backproject_points, adding |contribution| of every view. */
+int oracle_backproject_points_abs(double *out, const int *xyz, long n, const float *proj, int W, int H,
+                                  int n_views, const double *P, double MM, const double *O, int n_threads)
+{
+    return backproject_list(out, xyz, n, proj, W, H, n_views, P, MM, O, n_threads, 1);
+}
+
+/* Bilinear interpolant of one zero-extended image at one position (exported for pins). */
+double oracle_interpolate(const float *img, int W, int H, double s, double t)
+{
+    return interpolate(img, W, H, s, t);
 }

@@ -258,3 +258,35 @@ def pin_points_equal_blocks(lib):
 
 
 ALL_PINS.append(pin_points_equal_blocks)
+
+
+def pin_absolute(lib):
+    """The magnitude mode adds |contribution| of every view: the sum of the single-view
+    magnitudes, equal to the back projection itself for non-negative images, unchanged when the
+    images change sign, never below |V| and above it where signed contributions cancel; the
+    voxel-list entry agrees with the block entry."""
+    _, P = small_scan(n_views=5)
+    P = _P32(P)
+    W, H = SMALL_SCAN["W"], SMALL_SCAN["H"]
+    L, vs = 9, 22.0
+    origin = [-(L - 1) / 2 * vs] * 3
+    rng = np.random.default_rng(21)
+    I = rng.uniform(-1, 1, size=(5, H, W)).astype(np.float32)
+    V = oracle.backproject(I, P, L, vs, origin, lib=lib)
+    A = oracle.backproject(I, P, L, vs, origin, lib=lib, absolute=True)
+    singles = [np.abs(oracle.backproject(I[k:k + 1], P[k:k + 1], L, vs, origin, lib=lib)) for k in range(5)]
+    want = np.zeros_like(A)
+    for a in singles:  # the same order of additions as the oracle's views
+        want = want + a
+    assert np.array_equal(A, want), "magnitude mode is not the sum of single-view magnitudes"
+    assert np.array_equal(oracle.backproject(-I, P, L, vs, origin, lib=lib, absolute=True), A)
+    assert (A >= np.abs(V)).all() and (A > np.abs(V) * (1 + 1e-9)).any()
+    Ipos = np.abs(I)
+    assert np.array_equal(oracle.backproject(Ipos, P, L, vs, origin, lib=lib, absolute=True),
+                          oracle.backproject(Ipos, P, L, vs, origin, lib=lib))
+    xyz = rng.integers(0, L, size=(40, 3))
+    got = oracle.backproject_points(I, P, vs, origin, xyz, lib=lib, absolute=True)
+    assert np.array_equal(got, A[xyz[:, 2], xyz[:, 1], xyz[:, 0]])
+
+
+ALL_PINS.append(pin_absolute)

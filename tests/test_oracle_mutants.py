@@ -15,28 +15,36 @@ import oracle_pins as pins
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bp_oracle.c")
 
 MUTANTS = {
-    "trunc_not_floor": ("double fx = floor(ix), fy = floor(iy);", "double fx = trunc(ix), fy = trunc(iy);"),
+    # (truncation instead of floor is no mistake here: the tent weights of the taps it would
+    # pick wrongly are 0, so the sum is unchanged -- an equivalent mutant, not planted)
+    "nearest_not_floor": ("const long c0 = (long)floor(s), r0 = (long)floor(t);",
+                          "const long c0 = (long)round(s), r0 = (long)round(t);"),
     "bounds_swapped": ("if (i < 0 || i >= W || j < 0 || j >= H)", "if (i < 0 || i >= H || j < 0 || j >= W)"),
     "weight_1_over_w": ("return val / (w * w);", "return val / w;"),
     "matrix_transposed": ("double u = A[0] * wx + A[1] * wy + A[2] * wz + A[3];",
                           "double u = A[0] * wx + A[3] * wy + A[6] * wz + A[9];"),
-    "taps_swapped": ("double valtl = pixel(img, W, H, iix, iiy + 1);",
-                     "double valtl = pixel(img, W, H, iix + 1, iiy);"),
-    "fraction_sign": ("double scalex = ix - fx;", "double scalex = fx - ix;"),
-    "weight_rows_swapped": ("return (1.0 - scaley) * valb + scaley * valt;",
-                            "return scaley * valb + (1.0 - scaley) * valt;"),
+    "taps_transposed": ("sum += pixel(img, W, H, i, j) * tent(s - (double)i) * wt;",
+                        "sum += pixel(img, W, H, j, i) * tent(s - (double)i) * wt;"),
+    "column_weight_from_row": ("sum += pixel(img, W, H, i, j) * tent(s - (double)i) * wt;",
+                               "sum += pixel(img, W, H, i, j) * tent(t - (double)i) * wt;"),
+    "neighbourhood_to_the_left": ("for (long i = c0; i <= c0 + 1; ++i)", "for (long i = c0 - 1; i <= c0; ++i)"),
+    "row_weights_swapped": ("const double wt = tent(t - (double)j);", "const double wt = 1.0 - tent(t - (double)j);"),
     "no_w_test": ("if (!(w > 0.0))\n        return 0.0;", "if (0)\n        return 0.0;"),
     "voxel_corner_not_centre": ("double wx = jb->O[0] + jb->MM * (double)(jb->x0 + ix);",
                                 "double wx = jb->O[0] + jb->MM * ((double)(jb->x0 + ix) + 0.5);"),
     "dropped_v_offset": ("double v = A[4] * wx + A[5] * wy + A[6] * wz + A[7];",
                          "double v = A[4] * wx + A[5] * wy + A[6] * wz;"),
-    "edge_guard_open": ("if (!(ix > -1.0 && ix < (double)W && iy > -1.0 && iy < (double)H))",
-                        "if (!(ix > 0.0 && ix < (double)W && iy > -1.0 && iy < (double)H))"),
-    "skip_first_view": ("                for (int k = 0; k < jb->n_views; ++k)",
-                        "                for (int k = 1; k < jb->n_views; ++k)"),
-    "points_skip_last_view": ("        for (int k = 0; k < jb->n_views; ++k)\n            sum +=",
-                              "        for (int k = 0; k < jb->n_views - 1; ++k)\n            sum +="),
+    "edge_guard_open": ("if (!(s > -1.0 && s < (double)W && t > -1.0 && t < (double)H))",
+                        "if (!(s > 0.0 && s < (double)W && t > -1.0 && t < (double)H))"),
+    "skip_first_view": ("                for (int k = 0; k < jb->n_views; ++k) {",
+                        "                for (int k = 1; k < jb->n_views; ++k) {"),
+    "points_skip_last_view": ("        for (int k = 0; k < jb->n_views; ++k) {\n            const double c",
+                              "        for (int k = 0; k < jb->n_views - 1; ++k) {\n            const double c"),
     "overwrite_not_accumulate": ("double sum = *voxel;", "double sum = 0.0;"),
+    "magnitude_mode_signed": ("                    sum += jb->absolute ? fabs(c) : c;",
+                              "                    sum += c;"),
+    "points_magnitude_mode_signed": ("jb->P + 12 * (long)k, wx, wy, wz);\n            sum += jb->absolute ? fabs(c) : c;",
+                                     "jb->P + 12 * (long)k, wx, wy, wz);\n            sum += c;"),
 }
 
 

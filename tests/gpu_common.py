@@ -16,11 +16,16 @@ TORCH_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat1
 # the compared voxels.
 REL_L2_TOL = 1e-5
 
+# Element-wise companion of the relative-L2 bar (reading R12): max |error| over max |V_ref|.
+MAX_ABS_TOL = 1e-4
+
 # Compact staging rounds the bilinear-patch coefficients (pixel differences) to
 # FP16: unit roundoff u = 2^-11 on each of dx, dy, dxy.  The interpolated value
 # moves by at most u (|dx| + |dy| + |dxy|), which is of the order of u times the
 # local pixel magnitude; the bar on relative L2 is 2u.
 COMPACT_REL_L2_TOL = 2.0 ** -10
+# ... and its element-wise companion, in the same ratio to the relative-L2 bar as for FP32.
+COMPACT_MAX_ABS_TOL = COMPACT_REL_L2_TOL * (MAX_ABS_TOL / REL_L2_TOL)
 
 
 def rel_l2(got, ref):
@@ -51,7 +56,7 @@ def product_matrices(scanner):
 
 
 def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0, zu=0, init=None,
-            stream=None, tx=0, wide_staging=None):
+            stream=None, tx=0, wide_staging=None, cubic=False):
     """Back project on cuda:0 through the C ABI; returns the volume as a float32 numpy array."""
     dev = torch.device("cuda:0")
     nz, ny, nx = shape
@@ -65,7 +70,7 @@ def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0,
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning(path, k, zu, tx)
         ctx.set_options(wide_staging=wide_staging)
-        ctx.backproject(vol, p, m, voxel_size, origin, stream)
+        ctx.backproject(vol, p, m, voxel_size, origin, stream, cubic=cubic)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
 

@@ -175,6 +175,15 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     as 16-byte patch records rather than as the caller's FP32
  *                     pixels (from which each update then forms its patch with
  *                     the staging copy's own FP32 operations).  Bit-identical.
+ *   BP_OPT_POISON_STAGING  testing aid, fused path: fill each pass's staging copy
+ *                     with NaN before the views are staged into it, and (LDS
+ *                     stage, z_unroll 8 only; other z-unrolls: BP_ERR_UNSUPPORTED)
+ *                     the LDS stage before each footprint is copied in, so that
+ *                     any read of an element the staging did not write shows as
+ *                     NaN in the result.  Results are bit-identical otherwise.
+ *   BP_OPT_SINGLE_TAPS  paths on the caller's FP32 images (PLAIN, FUSED_DIRECT):
+ *                     load each tap as one dword instead of each row's pixel
+ *                     pair as one 8-byte load.  Bit-identical.
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of
@@ -196,6 +205,8 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_SERIAL_STAGING (1 << 10)
 #define BP_OPT_OVERLAP_STAGING (1 << 11)
 #define BP_OPT_STAGE_RECORDS (1 << 12)
+#define BP_OPT_POISON_STAGING (1 << 13)
+#define BP_OPT_SINGLE_TAPS (1 << 14)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* Fused path with LDS staging: of every 8 consecutive views of a pass, how many
@@ -212,6 +223,14 @@ bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
  * boxes of 2e8 voxels or more. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
                         bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x, int *direct_taps);
+
+/* Bytes of device scratch that the next call of size nx*ny*nz with n_views views on this context
+ * needs with its current settings: per-view constants, the staging copy of a pass (two when the
+ * next pass is staged while one runs), staging scales, the footprint tables or the clipping
+ * mask.  A context keeps the largest scratch of its calls until bp_destroy, so a caller that
+ * admits work by device memory (a server) counts max(held, this) per context.
+ * BP_ERR_INVALID_ARG for a null ctx or bytes, or a size below 1. */
+bp_status bp_query_scratch(bp_ctx ctx, int nx, int ny, int nz, int n_views, size_t *bytes);
 
 /*
  * Compose the projection matrices of a circular cone-beam orbit on the host

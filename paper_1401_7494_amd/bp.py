@@ -63,6 +63,7 @@ SIGNATURES = {
     "bp_query_plan": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int)]),
+    "bp_query_scratch": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "bp_circular_matrices": (_c_int, [_vp, _c_int, _c_double, _c_double, _c_double, _c_int, _c_int, _vp, _vp]),
     "bp_enable_timing": (_c_int, [_vp, _c_int]),
     "bp_kernel_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong)]),
@@ -191,17 +192,22 @@ class Context:
     OPT_SERIAL_STAGING = 1 << 10
     OPT_OVERLAP_STAGING = 1 << 11
     OPT_STAGE_RECORDS = 1 << 12
+    OPT_POISON_STAGING = 1 << 13
+    OPT_SINGLE_TAPS = 1 << 14
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
                     order: str = "region", region_ax: int = 0, direct_taps: bool = False,
-                    staging: str = "auto", stage_records: bool = False):
+                    staging: str = "auto", stage_records: bool = False, poison_staging: bool = False,
+                    single_taps: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
         projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
         each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices"); read every tap
         of the fused path directly instead of staging most views' footprints through LDS; stage the
         next pass while one runs ("overlap"), just before it ("serial") or as tuned ("auto":
-        overlapped for compact 16-bit records)."""
+        overlapped for compact 16-bit records); ``poison_staging`` (testing aid) fills the staging copy
+        and the LDS stage with NaN before each is written; ``single_taps`` reads the caller's FP32
+        pixels one dword per tap (instead of one 8-byte load per row pair)."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
                  | (self.OPT_WIDE_STAGING if wide_staging else 0))
         if order == "plain":
@@ -221,6 +227,10 @@ class Context:
             flags |= self.OPT_OVERLAP_STAGING
         if stage_records:
             flags |= self.OPT_STAGE_RECORDS
+        if poison_staging:
+            flags |= self.OPT_POISON_STAGING
+        if single_taps:
+            flags |= self.OPT_SINGLE_TAPS
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     def set_tap_split(self, direct_eighths: int = -1):
@@ -246,8 +256,17 @@ class Context:
                                         ctypes.byref(z), ctypes.byref(t), ctypes.byref(d)), "bp_query_plan")
         return Plan(PATH_NAMES[p.value], k.value, z.value, t.value, bool(d.value))
 
-    def backproject(self, volume, projections, matrices, voxel_size, origin, stream=None) -> None:
+    def scratch_bytes(self, nx, ny, nz, n_views) -> int:
+        """Device scratch (bytes) a call of this size needs with the context's current settings."""
+        b = ctypes.c_size_t()
+        self._check(lib().bp_query_scratch(self._h, nx, ny, nz, n_views, ctypes.byref(b)), "bp_query_scratch")
+        return b.value
+
+    def backproject(self, volume, projections, matrices, voxel_size, origin, stream=None, cubic=False) -> None:
         """Accumulate ``projections`` (N, H, W) into ``volume`` (nz, ny, nx), asynchronously on ``stream``.
+
+        cubic: call the cubic entry ``bp_backproject`` (volume L x L x L) instead of
+        ``bp_backproject_box`` (the two compute the same).
 
         volume: contiguous float32 CUDA tensor.  projections: contiguous CUDA
         tensor of the context's dtype.  matrices: (N, 3, 4) or (N, 12)
@@ -270,6 +289,13 @@ class Context:
                 raise ValueError("tensor is not on the context's device")
         nz, ny, nx = volume.shape
         o = (ctypes.c_float * 3)(*[float(v) for v in origin])
+        if cubic:
+            if not nx == ny == nz:
+                raise ValueError("the cubic entry takes an L x L x L volume")
+            st = lib().bp_backproject(self._h, volume.data_ptr(), projections.data_ptr(), matrices.data_ptr(), n,
+                                      nx, float(voxel_size), o, _stream_handle(stream, self.device))
+            self._check(st, "bp_backproject")
+            return
         st = lib().bp_backproject_box(self._h, volume.data_ptr(), nx, ny, nz, projections.data_ptr(),
                                       matrices.data_ptr(), n, float(voxel_size), o, _stream_handle(stream, self.device))
         self._check(st, "bp_backproject_box")

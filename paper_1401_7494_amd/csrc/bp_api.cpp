@@ -49,7 +49,6 @@ struct bp_ctx_s {
     double total_ms[3] = {0, 0, 0};
     long long launches[3] = {0, 0, 0};
     std::vector<hipEvent_t> event_pool;
-
 };
 
 namespace {
@@ -243,7 +242,90 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
 
 bp::Dtype to_dt(bp_dtype d) { return static_cast<bp::Dtype>(static_cast<int>(d)); }
 
+size_t elem_bytes(bp_dtype d);
+
+// What one call of a given shape enqueues and the scratch it needs (bytes per buffer).
+struct CallShape {
+    Plan plan;
+    bp::Layout layout;
+    bool lds, culled, staged, raw_stage, overlap;
+    int split, words, halves;
+    long tiles;
+    size_t pad_half, fp_half, scale_half;
+    size_t views_bytes, pad_bytes, scale_bytes, cull_bytes, fp_bytes;
+    size_t total() const { return views_bytes + pad_bytes + scale_bytes + cull_bytes + fp_bytes; }
+};
+
+CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
+{
+    CallShape c;
+    const int W = ctx->cfg.det_width, H = ctx->cfg.det_height;
+    c.plan = plan_for(ctx, nx, ny, nz, n_views);
+    c.layout = c.plan.path == BP_PATH_FUSED ? bp::Layout::Patch : bp::Layout::Checked;
+    if (c.layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
+        c.layout = bp::Layout::Patch16;
+    // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
+    c.lds = !c.plan.direct_taps && staged_taps(ctx, c.layout, W, H);
+    c.culled = (c.layout != bp::Layout::Checked || c.plan.path == BP_PATH_FUSED_DIRECT) && !c.lds &&
+               !(ctx->options & BP_OPT_NO_CULL);
+    c.tiles = bp::n_tiles(nx, ny, nz, c.plan.zu, c.plan.tx);
+    // share of the views of each 8 that read directly while the others are staged (tuned at L = 512)
+    c.split = ctx->tap_split >= 0 ? ctx->tap_split : (c.layout == bp::Layout::Patch ? 4 : 3);
+    c.words = bp::cull_words(n_views);
+    // Staging of the next pass overlaps the current pass when there are two or more passes.  Tuned:
+    // compact records only (L = 512, 496 views: BF16 2068 -> 2151 GUPS); the FP32 staging kernel
+    // contends with the pass for the vector memory path, and the pass slows by what the overlap hides.
+    c.staged = c.layout != bp::Layout::Checked;
+    // FP32 input: the LDS stage holds the caller's pixels (a quarter of the bytes of the records)
+    c.raw_stage = c.lds && c.layout == bp::Layout::Patch && ctx->cfg.proj_dtype == BP_F32 &&
+                  !(ctx->options & BP_OPT_STAGE_RECORDS);
+    c.overlap = c.staged && n_views > c.plan.k && !(ctx->options & BP_OPT_SERIAL_STAGING) &&
+                (c.layout == bp::Layout::Patch16 || (ctx->options & BP_OPT_OVERLAP_STAGING));
+    c.halves = c.overlap ? 2 : 1;
+    c.pad_half = bp::staged_view_bytes(c.layout, W, H) * (size_t)c.plan.k;
+    c.fp_half = (size_t)c.tiles * (size_t)c.plan.k;  // uint2 entries
+    c.scale_half = 8u * (size_t)c.plan.k;            // bytes: max |pixel| bits, then 2^-e scales
+    c.views_bytes = sizeof(bp::ViewConst) * (size_t)n_views;
+    c.pad_bytes = c.staged ? c.pad_half * c.halves : 0;
+    c.scale_bytes = c.staged && (c.layout == bp::Layout::Patch16 || c.raw_stage) ? c.scale_half * c.halves : 0;
+    c.cull_bytes = c.culled ? (size_t)c.tiles * (size_t)c.words * 4u : 0;
+    c.fp_bytes = c.lds ? c.fp_half * c.halves * sizeof(uint2) : 0;
+    return c;
+}
+
 size_t elem_bytes(bp_dtype d) { return d == BP_F32 ? 4 : 2; }
+
+// Argument checks shared by the entry points (nothing is enqueued when one fails).
+bp_status check_call(bp_ctx ctx, const float* volume, int nx, int ny, int nz, const void* projections,
+                     const float* matrices, int n_views, float voxel_size, const float origin[3])
+{
+    if (!volume || !projections || !matrices || !origin)
+        return fail(ctx, BP_ERR_INVALID_ARG, "null pointer argument");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, BP_ERR_INVALID_ARG, "volume dimensions must be >= 1");
+    if ((uint64_t)nx * (uint64_t)ny * (uint64_t)nz >= ((uint64_t)1 << 40))
+        return fail(ctx, BP_ERR_INVALID_ARG, "volume too large");
+    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24))
+        return fail(ctx, BP_ERR_INVALID_ARG, "volume edge beyond 2^24 voxels");
+    if (n_views < 1) return fail(ctx, BP_ERR_INVALID_ARG, "n_views must be >= 1");
+    if (!std::isfinite(voxel_size) || !(voxel_size > 0.0f))
+        return fail(ctx, BP_ERR_INVALID_ARG, "voxel_size must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(origin[a])) return fail(ctx, BP_ERR_INVALID_ARG, "origin must be finite");
+    if (reinterpret_cast<uintptr_t>(volume) % 4 != 0 || reinterpret_cast<uintptr_t>(matrices) % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(projections) % elem_bytes(ctx->cfg.proj_dtype) != 0)
+        return fail(ctx, BP_ERR_INVALID_ARG, "misaligned device pointer");
+    return BP_OK;
+}
+
+// tile order: XCD z-slices (opt-in), plain (opt-in), else XCD-private regions of each z-layer
+int tile_order(const bp_ctx_s* ctx)
+{
+    int xcd_order = 2 * kDefaultRegionAx;
+    if (const int r = (ctx->options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT) xcd_order = 2 * r;
+    if (ctx->options & BP_OPT_PLAIN_ORDER) xcd_order = 0;
+    if (ctx->options & BP_OPT_XCD_ORDER) xcd_order = 1;
+    return xcd_order;
+}
 
 }  // namespace
 
@@ -374,11 +456,19 @@ bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views, bp_path
     return BP_OK;
 }
 
+bp_status bp_query_scratch(bp_ctx ctx, int nx, int ny, int nz, int n_views, size_t* bytes)
+{
+    if (!ctx || !bytes || nx < 1 || ny < 1 || nz < 1 || n_views < 1) return BP_ERR_INVALID_ARG;
+    *bytes = call_shape(ctx, nx, ny, nz, n_views).total();
+    return BP_OK;
+}
+
 bp_status bp_set_options(bp_ctx ctx, int options)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
-                    BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS | BP_OPT_SERIAL_STAGING | BP_OPT_OVERLAP_STAGING | BP_OPT_STAGE_RECORDS))
+                    BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS | BP_OPT_SERIAL_STAGING | BP_OPT_OVERLAP_STAGING |
+                    BP_OPT_STAGE_RECORDS | BP_OPT_POISON_STAGING | BP_OPT_SINGLE_TAPS))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
     if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
@@ -417,24 +507,12 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                              void* stream)
 {
     if (!ctx) return BP_ERR_INVALID_ARG;
-    if (!volume || !projections || !matrices || !origin)
-        return fail(ctx, BP_ERR_INVALID_ARG, "null pointer argument");
-    if (nx < 1 || ny < 1 || nz < 1) return fail(ctx, BP_ERR_INVALID_ARG, "volume dimensions must be >= 1");
-    if ((uint64_t)nx * (uint64_t)ny * (uint64_t)nz >= ((uint64_t)1 << 40))
-        return fail(ctx, BP_ERR_INVALID_ARG, "volume too large");
-    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24))
-        return fail(ctx, BP_ERR_INVALID_ARG, "volume edge beyond 2^24 voxels");
-    if (n_views < 1) return fail(ctx, BP_ERR_INVALID_ARG, "n_views must be >= 1");
-    if (!std::isfinite(voxel_size) || !(voxel_size > 0.0f))
-        return fail(ctx, BP_ERR_INVALID_ARG, "voxel_size must be finite and > 0");
-    for (int a = 0; a < 3; ++a)
-        if (!std::isfinite(origin[a])) return fail(ctx, BP_ERR_INVALID_ARG, "origin must be finite");
-    if (reinterpret_cast<uintptr_t>(volume) % 4 != 0 || reinterpret_cast<uintptr_t>(matrices) % 4 != 0 ||
-        reinterpret_cast<uintptr_t>(projections) % elem_bytes(ctx->cfg.proj_dtype) != 0)
-        return fail(ctx, BP_ERR_INVALID_ARG, "misaligned device pointer");
+    if (const bp_status st = check_call(ctx, volume, nx, ny, nz, projections, matrices, n_views, voxel_size, origin))
+        return st;
 
     const int W = ctx->cfg.det_width, H = ctx->cfg.det_height;
-    const Plan plan = plan_for(ctx, nx, ny, nz, n_views);
+    const CallShape cs = call_shape(ctx, nx, ny, nz, n_views);
+    const Plan& plan = cs.plan;
     const bp::Box box{nx, ny, nz, voxel_size, origin[0], origin[1], origin[2]};
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const bp::Dtype dt = to_dt(ctx->cfg.proj_dtype);
@@ -442,50 +520,32 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     DeviceGuard g(ctx->cfg.device);
     if (!g.ok) return fail(ctx, BP_ERR_DEVICE, "cannot select the context's device");
 
-    bp::Layout layout = plan.path == BP_PATH_FUSED ? bp::Layout::Patch : bp::Layout::Checked;
-    if (layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
-        layout = bp::Layout::Patch16;
-    // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
-    const bool lds = !plan.direct_taps && staged_taps(ctx, layout, W, H);
-    const bool culled = (layout != bp::Layout::Checked || plan.path == BP_PATH_FUSED_DIRECT) && !lds &&
-                        !(ctx->options & BP_OPT_NO_CULL);
-    const long tiles = bp::n_tiles(nx, ny, nz, plan.zu, plan.tx);
-    // share of the views of each 8 that read directly while the others are staged (tuned at L = 512)
-    const int split = ctx->tap_split >= 0 ? ctx->tap_split : (layout == bp::Layout::Patch ? 4 : 3);
-    const int words = bp::cull_words(n_views);
-
-    // Staging of the next pass overlaps the current pass when there are two or more passes.  Tuned:
-    // compact records only (L = 512, 496 views: BF16 2068 -> 2151 GUPS); the FP32 staging kernel
-    // contends with the pass for the vector memory path, and the pass slows by what the overlap hides.
-    const bool staged = layout != bp::Layout::Checked;
-    // FP32 input: the LDS stage holds the caller's pixels (a quarter of the bytes of the records)
-    const bool raw_stage = lds && layout == bp::Layout::Patch && dt == bp::Dtype::F32 &&
-                           !(ctx->options & BP_OPT_STAGE_RECORDS);
-    const bool overlap = staged && n_views > plan.k && !(ctx->options & BP_OPT_SERIAL_STAGING) &&
-                         (layout == bp::Layout::Patch16 || (ctx->options & BP_OPT_OVERLAP_STAGING));
-    const int halves = overlap ? 2 : 1;
-    const size_t pad_half = bp::staged_view_bytes(layout, W, H) * (size_t)plan.k;
-    const size_t fp_half = (size_t)tiles * (size_t)plan.k;  // uint2 entries
-    const size_t scale_half = 8u * (size_t)plan.k;          // bytes: max |pixel| bits, then 2^-e scales
+    const bp::Layout layout = cs.layout;
+    const bool lds = cs.lds, culled = cs.culled, staged = cs.staged, raw_stage = cs.raw_stage, overlap = cs.overlap;
+    const int split = cs.split, words = cs.words;
+    const size_t pad_half = cs.pad_half, fp_half = cs.fp_half, scale_half = cs.scale_half;
+    const bool poison = (ctx->options & BP_OPT_POISON_STAGING) != 0;
+    if (poison && lds && plan.zu != 8)
+        return fail(ctx, BP_ERR_UNSUPPORTED, "poisoned staging runs the LDS pass with z_unroll 8 only");
 
     // all scratch first: a call that fails here has enqueued nothing
-    bp_status st = ensure(ctx, reinterpret_cast<void**>(&ctx->d_views), &ctx->views_cap,
-                          sizeof(bp::ViewConst) * (size_t)n_views, "view constants");
+    bp_status st = ensure(ctx, reinterpret_cast<void**>(&ctx->d_views), &ctx->views_cap, cs.views_bytes,
+                          "view constants");
     if (st != BP_OK) return st;
-    if (staged) {
-        st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, pad_half * halves, "staged projections");
-        if (st != BP_OK) return st;
-        if (layout == bp::Layout::Patch16 || raw_stage) {
-            st = ensure(ctx, &ctx->d_scale, &ctx->scale_cap, scale_half * halves, "staging scales");
-            if (st != BP_OK) return st;
-        }
-    }
-    if (culled) {
-        st = ensure(ctx, &ctx->d_cull, &ctx->cull_cap, (size_t)tiles * (size_t)words * 4u, "clipping mask");
+    if (cs.pad_bytes) {
+        st = ensure(ctx, &ctx->d_pad, &ctx->pad_cap, cs.pad_bytes, "staged projections");
         if (st != BP_OK) return st;
     }
-    if (lds) {
-        st = ensure(ctx, &ctx->d_fp, &ctx->fp_cap, fp_half * halves * sizeof(uint2), "footprints");
+    if (cs.scale_bytes) {
+        st = ensure(ctx, &ctx->d_scale, &ctx->scale_cap, cs.scale_bytes, "staging scales");
+        if (st != BP_OK) return st;
+    }
+    if (cs.cull_bytes) {
+        st = ensure(ctx, &ctx->d_cull, &ctx->cull_cap, cs.cull_bytes, "clipping mask");
+        if (st != BP_OK) return st;
+    }
+    if (cs.fp_bytes) {
+        st = ensure(ctx, &ctx->d_fp, &ctx->fp_cap, cs.fp_bytes, "footprints");
         if (st != BP_OK) return st;
     }
     if (overlap && ensure_side(ctx) != BP_OK) return fail(ctx, BP_ERR_DEVICE, "cannot create the staging stream");
@@ -507,11 +567,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
     }
 
     const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
-    // tile order: XCD z-slices (opt-in), plain (opt-in), else XCD-private regions of each z-layer
-    int xcd_order = 2 * kDefaultRegionAx;
-    if (const int r = (ctx->options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT) xcd_order = 2 * r;
-    if (ctx->options & BP_OPT_PLAIN_ORDER) xcd_order = 0;
-    if (ctx->options & BP_OPT_XCD_ORDER) xcd_order = 1;
+    const int xcd_order = tile_order(ctx);
     // the side stream starts after the view constants (and everything before this call on s)
     const hipStream_t ss = overlap ? ctx->side : s;
     if (overlap && (hipEventRecord(ctx->ev_start, s) != hipSuccess || hipStreamWaitEvent(ss, ctx->ev_start, 0) != hipSuccess))
@@ -530,6 +586,10 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             // this half was last read by the pass two before
             if (overlap && pass >= 2 && hipStreamWaitEvent(ss, ctx->ev_done[half], 0) != hipSuccess)
                 return fail(ctx, BP_ERR_LAUNCH, "cannot order the staging stream");
+            if (poison) {  // testing aid: records no view of the pass writes stay NaN
+                e = bp::launch_fill(pad, pad_half, bp::kPoisonPattern, ss);
+                if (e != hipSuccess) return fail(ctx, BP_ERR_LAUNCH, std::string("fill kernel: ") + hipGetErrorString(e));
+            }
             // Footprints first: with pixel stages they flag the views whose records are read at all
             // (the scale scratch holds the pass's flags), and only those are staged as records.
             bp::ViewNeed need;
@@ -560,14 +620,16 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
                                               pad, W, H, cull, xcd_order, inv_scale, fp,
-                                              raw_stage ? static_cast<const float*>(src_views) : nullptr, s);
+                                              raw_stage ? static_cast<const float*>(src_views) : nullptr, s,
+                                              poison && lds);
             });
             if (e == hipSuccess && overlap && hipEventRecord(ctx->ev_done[half], s) != hipSuccess)
                 return fail(ctx, BP_ERR_LAUNCH, "cannot record the end of a pass");
         } else {
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
-                                              src_views, W, H, cull, xcd_order, nullptr, nullptr, nullptr, s);
+                                              src_views, W, H, cull, xcd_order, nullptr, nullptr, nullptr, s, false,
+                                              (ctx->options & BP_OPT_SINGLE_TAPS) != 0);
             });
         }
         if (e != hipSuccess)

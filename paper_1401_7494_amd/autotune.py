@@ -4,7 +4,11 @@ For one problem shape -- box (nx, ny, nz), views, storage dtype, detector --
 it times every candidate (path, views per pass K, z-unroll ZU) on the device
 and keeps the fastest, as the median of a few timed runs after a warm-up.
 Results are cached in a JSON file keyed by device name and shape, and applied
-to a context with ``bp_set_tuning``.
+to a context with ``bp_set_tuning`` (and the tap options).  ``ensure_tuned``
+is what the benchmark and the serving executor call: it reads the cache for
+the call's shape and device, searches only on a miss, and applies the winner.
+The library's own automatic choice (``AUTO``) is always one of the timed
+candidates, so a tuned launch is never slower than it on the timed runs.
 
 The timing function is injectable, so the search logic is testable without a
 GPU.
@@ -35,6 +39,10 @@ class Candidate:
     def key(self) -> str:
         return (f"{self.path}/{self.views_per_pass}/{self.z_unroll}/{self.tile_x}/"
                 f"{'direct' if self.direct_taps else self.tap_split}")
+
+
+# The library's own choice for the call (BP_PATH_AUTO with every parameter tuned by the library).
+AUTO = Candidate("auto", 0, 0, 0, -1, False)
 
 
 @dataclass(frozen=True)
@@ -146,11 +154,61 @@ def tune_on_device(ctx, volume, projections, matrices, voxel_size, origin, cands
     return result
 
 
-def apply(ctx, cand: Candidate) -> None:
-    """Set the candidate's choices on a context (its options other than the tap mode are reset)."""
+def apply(ctx, cand: Candidate, **options) -> None:
+    """Set the candidate's choices on a context; its options are reset to ``options`` plus the
+    candidate's tap mode."""
     ctx.set_tuning(cand.path, cand.views_per_pass, cand.z_unroll, cand.tile_x)
-    ctx.set_options(direct_taps=cand.direct_taps)
+    ctx.set_options(direct_taps=cand.direct_taps, **options)
     ctx.set_tap_split(cand.tap_split)
+
+
+def problem_of(ctx, volume_shape, n_views) -> Problem:
+    nz, ny, nx = volume_shape
+    return Problem(nx, ny, nz, n_views, ctx.dtype, ctx.det_width, ctx.det_height)
+
+
+def ensure_tuned(ctx, volume, projections, matrices, voxel_size, origin, cands=None, reps=2, warmup=1,
+                 cache_path: str | None = DEFAULT_CACHE, device_name: str | None = None, time_fn=None):
+    """The tuned launch for this call's shape on this device, applied to ``ctx``.
+
+    Reads the cache (key: device name and problem shape); on a miss times ``cands`` (plus the
+    library's automatic choice) on the device, stores the result and applies the winner.
+    ``volume`` is used as scratch by the search (its contents are left undefined).  Returns
+    ``(candidate, info)`` with info = {"source": "cache" | "search", "auto_ms", "best_ms",
+    "timings_ms"} (times only for a search).  ``time_fn`` replaces the device timer (tests)."""
+    problem = problem_of(ctx, volume.shape, projections.shape[0])
+    if device_name is None:
+        import torch
+
+        device_name = torch.cuda.get_device_name(volume.device)
+    dev = device_name
+    key = problem.key(dev)
+    if cache_path:
+        hit = lookup(key, cache_path)
+        if hit is not None:
+            apply(ctx, hit)
+            return hit, {"source": "cache", "key": key}
+    cands = list(cands) if cands is not None else candidates(problem)
+    if AUTO not in cands:
+        cands.insert(0, AUTO)
+    if time_fn is None:
+        import torch
+
+        time_fn = device_timer(ctx, volume, projections, matrices, voxel_size, origin, torch)
+    res = search(problem, time_fn, cands, reps=reps, warmup=warmup)
+    if cache_path:
+        store(key, res, cache_path)
+    apply(ctx, res.best)
+    return res.best, {"source": "search", "key": key, "auto_ms": res.timings_ms[AUTO.key()],
+                      "best_ms": res.timings_ms[res.best.key()], "timings_ms": res.timings_ms}
+
+
+def lookup_and_apply(ctx, volume_shape, n_views, device_name: str, cache_path: str = DEFAULT_CACHE):
+    """Apply the cached tuned launch for this shape if there is one (else the library's automatic
+    choice); returns the candidate applied."""
+    hit = lookup(problem_of(ctx, volume_shape, n_views).key(device_name), cache_path) if cache_path else None
+    apply(ctx, hit or AUTO)
+    return hit or AUTO
 
 
 def _csv_ints(s):

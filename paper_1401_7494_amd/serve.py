@@ -13,6 +13,12 @@ Latency is measured from arrival to the volume being ready; the device time
 of the ingest and of the back projection are recorded separately (HIP events
 on the request's stream).
 
+A request can be withdrawn (``Request.cancel_s``, or ``Server.cancel(rid)``
+from another thread): one still waiting leaves the queue at once; one in
+flight is handed to the executor's ``cancel``, its result is dropped, and its
+memory is released when the executor reports its device work over (work
+already enqueued on the GPU runs to its end).
+
 The executor does the device work; ``FakeExecutor`` stands in for it with
 simulated durations so the scheduling logic is testable on the CPU.
 """
@@ -56,6 +62,7 @@ class Report:
     peak_bytes: int
     peak_inflight: int
     rejected: list = field(default_factory=list)
+    cancelled: list = field(default_factory=list)  # (rid, "waiting" | "inflight", time s)
 
     def latencies(self):
         return np.array([c.latency_s for c in self.completed])
@@ -75,6 +82,7 @@ class Report:
         return {
             "requests": len(self.completed),
             "rejected": len(self.rejected),
+            "cancelled": len(self.cancelled),
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
             "mean_queue_ms": float(np.mean([c.queue_s for c in self.completed]) * 1e3) if len(lat) else None,
@@ -91,22 +99,38 @@ class Server:
 
     def __init__(self, executor, budget_bytes: int, max_inflight: int = 8, clock=time.perf_counter,
                  sleep=time.sleep, poll_s: float = 2e-4):
+        import threading
+
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_inflight = int(max_inflight)
         self.clock = clock
         self.sleep = sleep
         self.poll_s = poll_s
+        self._lock = threading.Lock()
+        self._cancel = set()
+
+    def cancel(self, rid: int) -> None:
+        """Withdraw request ``rid`` (safe to call from another thread while ``run`` is going)."""
+        with self._lock:
+            self._cancel.add(rid)
+
+    def _withdrawn(self, r, now) -> bool:
+        if r.cancel_s is not None and r.cancel_s <= now:
+            return True
+        with self._lock:
+            return r.rid in self._cancel
 
     def run(self, requests) -> Report:
         pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         waiting = []  # arrived, not admitted (FIFO)
         inflight = {}  # rid -> (handle, request, footprint, admitted_s)
+        draining = {}  # cancelled in flight: rid -> (handle, footprint), memory held until the work ends
         used = peak = peak_n = 0
-        done, rejected = [], []
+        done, rejected, cancelled = [], [], []
         t0 = self.clock()
         i = 0
-        while i < len(pending) or waiting or inflight:
+        while i < len(pending) or waiting or inflight or draining:
             now = self.clock() - t0
             while i < len(pending) and pending[i].arrival_s <= now:
                 r = pending[i]
@@ -116,6 +140,26 @@ class Server:
                 else:
                     waiting.append(r)
             progressed = False
+            # withdrawn requests: waiting ones leave the queue, running ones are told to stop
+            for r in [r for r in waiting if self._withdrawn(r, now)]:
+                waiting.remove(r)
+                cancelled.append((r.rid, "waiting", now))
+                progressed = True
+            for rid in list(inflight):
+                h, r, fp, adm = inflight[rid]
+                if self._withdrawn(r, now):
+                    self.ex.cancel(h)
+                    draining[rid] = (h, fp)
+                    del inflight[rid]
+                    cancelled.append((rid, "inflight", now))
+                    progressed = True
+            for rid in list(draining):
+                h, fp = draining[rid]
+                if self.ex.poll(h):
+                    self.ex.discard(h)
+                    used -= fp
+                    del draining[rid]
+                    progressed = True
             # completions free memory and slots
             for rid in list(inflight):
                 h, r, fp, adm = inflight[rid]
@@ -128,7 +172,7 @@ class Server:
                     progressed = True
             # admit the oldest arrived requests that fit (a large one does not block smaller ones behind it)
             for r in list(waiting):
-                if len(inflight) >= self.max_inflight:
+                if len(inflight) + len(draining) >= self.max_inflight:
                     break
                 fp = self.ex.footprint(r)
                 if used + fp <= self.budget:
@@ -137,7 +181,7 @@ class Server:
                     inflight[r.rid] = (self.ex.start(r), r, fp, adm)
                     used += fp
                     peak = max(peak, used)
-                    peak_n = max(peak_n, len(inflight))
+                    peak_n = max(peak_n, len(inflight) + len(draining))
                     progressed = True
             if not progressed:
                 nxt = pending[i].arrival_s - (self.clock() - t0) if i < len(pending) else None
@@ -145,7 +189,7 @@ class Server:
                 if inflight and nxt is not None:
                     wait = min(self.poll_s, max(nxt, 0.0))
                 self.sleep(max(wait, 0.0))
-        return Report(done, self.clock() - t0, peak, peak_n, rejected)
+        return Report(done, self.clock() - t0, peak, peak_n, rejected, cancelled)
 
 
 # ---------------------------------------------------------------------------
@@ -169,6 +213,7 @@ class FakeExecutor:
         self.rate = rate_ups
         self.t_fixed = t_fixed
         self.started = []
+        self.discarded = []
         self.bytes_per_pixel = bytes_per_pixel or {"f32": 4, "f16": 2, "bf16": 2}
 
     def updates(self, r) -> float:
@@ -180,13 +225,20 @@ class FakeExecutor:
 
     def start(self, r):
         self.started.append(r.rid)
-        return (r, self.clock() + self.t_fixed + self.updates(r) / self.rate)
+        return (r, self.clock() + self.t_fixed + self.updates(r) / self.rate, {"stop": None})
 
     def poll(self, h) -> bool:
-        return self.clock() >= h[1]
+        return self.clock() >= (h[1] if h[2]["stop"] is None else h[2]["stop"])
 
     def finish(self, h):
         return h[0].rid, {}
+
+    def cancel(self, h):
+        """The simulated device stops a cancelled request at once."""
+        h[2]["stop"] = self.clock()
+
+    def discard(self, h):
+        self.discarded.append(h[0].rid)
 
 
 class GpuExecutor:
@@ -198,7 +250,7 @@ class GpuExecutor:
     keep_results: return each volume (on the host) from ``finish``; otherwise a checksum."""
 
     def __init__(self, device=0, keep_results=False, views_per_pass=0, z_unroll=0, tile_x=0,
-                 scanner_fn=request_scanner, volume_fn=request_volume, fast_inputs=True):
+                 scanner_fn=request_scanner, volume_fn=request_volume, fast_inputs=True, tuning_cache=None):
         import torch
 
         from . import bp
@@ -206,8 +258,11 @@ class GpuExecutor:
         self.torch = torch
         self.bp = bp
         self.dev = torch.device(f"cuda:{device}")
+        self.dev_name = torch.cuda.get_device_name(self.dev)
         self.keep = keep_results
         self.tuning = (views_per_pass, z_unroll, tile_x)
+        # autotune cache (path): a request whose shape has a tuned launch on this device runs it
+        self.tuning_cache = tuning_cache
         self.scanner_fn = scanner_fn
         self.volume_fn = volume_fn
         self.fast_inputs = fast_inputs
@@ -216,24 +271,45 @@ class GpuExecutor:
         # call on it, so one context serves one in-flight request at a time; contexts are
         # kept for the executor's lifetime (destroying one synchronises the device).
         self._free_ctx = {}
+        self._probe = {}  # one context per (dtype, W, H) that only answers scratch queries
         self._fdk = {}  # FDK handles per detector geometry (safe to share between streams)
 
     def updates(self, r) -> float:
         return float(r.L) ** 3 * r.n_views
 
+    def _tune(self, ctx, r, sc):
+        """The request's launch: the autotuner's for its shape if cached, else the executor's
+        fixed choices (0 = the library's)."""
+        if self.tuning_cache:
+            from . import autotune
+
+            hit = autotune.lookup(autotune.Problem(r.L, r.L, r.L, r.n_views, r.dtype, sc.W, sc.H).key(self.dev_name),
+                                  self.tuning_cache)
+            if hit is not None:
+                autotune.apply(ctx, hit)
+                return hit
+        ctx.set_tuning("auto", *self.tuning)
+        ctx.set_options()
+        ctx.set_tap_split(-1)
+        return None
+
     def footprint(self, r) -> int:
+        """Device bytes the request holds while in flight: volume, projections, raw input, the
+        generator's work arrays and the library's scratch for the call (as the library reports it
+        for the launch the request will run)."""
         sc = self.scanner_fn(r)
         bpp = 4 if r.dtype == "f32" else 2
         vol = 4 * r.L ** 3
         proj = r.n_views * sc.W * sc.H * bpp
-        k = min(r.n_views, self.tuning[0] or (64 if r.dtype == "f32" else 128))  # the library's default K
         raw = r.n_views * sc.W * sc.H * 4 if self.fast_inputs else 0
-        # compact records: two passes staged, the next one while one runs
-        staging = (2 if r.n_views > k and r.dtype != "f32" else 1) * k * (sc.W + 2) * (sc.H + 2) * (16 if r.dtype == "f32" else 8)
-        tiles = (r.L // 16 + 1) * (r.L // 16 + 1) * (r.L // 8 + 1)
-        cull = tiles * max((r.n_views + 31) // 32 * 4, 2 * k * 8)  # clipping mask or footprint tables
+        key = (r.dtype, sc.W, sc.H)
+        if key not in self._probe:
+            self._probe[key] = self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
+        probe = self._probe[key]
+        self._tune(probe, r, sc)
+        scratch = probe.scratch_bytes(r.L, r.L, r.L, r.n_views)
         gen = 6 * 62 * sc.W * sc.H * 8  # FP64 work arrays of the input generator (62 views at a time)
-        return vol + proj + raw + staging + cull + gen
+        return vol + proj + raw + scratch + gen
 
     def _matrices(self, sc):
         key = sc.geometry_args()[1:] + (sc.n_views, sc.arc_deg, sc.start_deg)
@@ -273,7 +349,7 @@ class GpuExecutor:
         key = (r.dtype, sc.W, sc.H)
         pool = self._free_ctx.setdefault(key, [])
         ctx = pool.pop() if pool else self.bp.Context(sc.W, sc.H, r.dtype, device=self.dev.index or 0)
-        ctx.set_tuning("auto", *self.tuning)
+        self._tune(ctx, r, sc)
         ctx.backproject(vol, proj, mats, v.voxel_size, v.origin, stream)
         ev[2].record(stream)
         return {"r": r, "stream": stream, "ctx": ctx, "key": key, "vol": vol, "proj": proj, "raw": raw,
@@ -291,7 +367,20 @@ class GpuExecutor:
         h.clear()
         return out, tm
 
+    def cancel(self, h):
+        """Work already enqueued for a cancelled request runs to its end (a kernel cannot be
+        stopped midway); its result is dropped by ``discard``."""
+        h["cancelled"] = True
+
+    def discard(self, h):
+        h["done"].synchronize()
+        self._free_ctx[h["key"]].append(h["ctx"])
+        h.clear()
+
     def close(self):
+        for ctx in self._probe.values():
+            ctx.close()
+        self._probe.clear()
         for pool in self._free_ctx.values():
             for ctx in pool:
                 ctx.close()
@@ -299,6 +388,36 @@ class GpuExecutor:
         for f in self._fdk.values():
             f.close()
         self._fdk.clear()
+
+
+def serve_mix(ex, n_requests=200, seed=1405, budget_bytes=200 * GIB, max_inflight=8, load=0.8, rate=0.0,
+              warmup=True, log=None):
+    """The serving measurement: first every request of the seeded mix is offered at time 0
+    (back-to-back capacity), then the same mix arrives as a Poisson stream at ``load`` times that
+    capacity (or at ``rate`` requests/s).  Returns (capacity summary or None, Poisson summary)."""
+    if warmup:
+        # not reported: contexts, FDK handles, scratch and the allocator reach their largest sizes
+        # for every storage dtype of the mix
+        warm = [synth.Request(-1 - i, 0.0, 512, 496, dt, 99999 - i) for i, dt in enumerate(("f32", "f16"))]
+        Server(ex, budget_bytes, max_inflight).run(warm)
+    base = synth.poisson_requests(n_requests, 1.0, seed)
+    cap_summary = None
+    if not rate:
+        burst = [synth.Request(r.rid, 0.0, r.L, r.n_views, r.dtype, r.phantom_seed) for r in base]
+        rep = Server(ex, budget_bytes, max_inflight).run(burst)
+        cap = len(rep.completed) / rep.makespan_s
+        cap_summary = rep.summary()
+        cap_summary.update(phase="back_to_back", capacity_rps=cap)
+        if log:
+            log(f"serve: capacity {cap_summary}")
+        rate = load * cap
+    stream = synth.poisson_requests(n_requests, rate, seed)
+    rep = Server(ex, budget_bytes, max_inflight).run(stream)
+    s = rep.summary()
+    s.update(phase="poisson", rate_rps=rate, load=load, budget_gib=budget_bytes / GIB, max_inflight=max_inflight)
+    if log:
+        log(f"serve: poisson {s}")
+    return cap_summary, s
 
 
 def main(argv=None):
@@ -318,30 +437,15 @@ def main(argv=None):
     ap.add_argument("--max-inflight", type=int, default=8)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of measured capacity")
     ap.add_argument("--rate", type=float, default=0.0, help="arrival rate (requests/s); 0 = load x capacity")
+    ap.add_argument("--tuning-cache", default=None, help="autotune cache to take each request's launch from")
     args = ap.parse_args(argv)
-    budget = int(args.budget_gib * GIB)
-    base = synth.poisson_requests(args.requests, 1.0, args.seed)
-    ex = GpuExecutor()
-    # warm-up (not reported): contexts, FDK handles, scratch and the allocator reach their
-    # largest sizes for every storage dtype of the mix
-    warm = [synth.Request(-1 - i, 0.0, 512, 496, dt, 99999 - i) for i, dt in enumerate(("f32", "f16"))]
-    Server(ex, budget, args.max_inflight).run(warm)
-    if not args.rate:
-        burst = [synth.Request(r.rid, 0.0, r.L, r.n_views, r.dtype, r.phantom_seed) for r in base]
-        rep = Server(ex, budget, args.max_inflight).run(burst)
-        cap = len(rep.completed) / rep.makespan_s
-        s = rep.summary()
-        s.update(phase="back_to_back", capacity_rps=cap)
-        print(json.dumps(s), flush=True)
-        rate = args.load * cap
-    else:
-        rate = args.rate
-    stream = synth.poisson_requests(args.requests, rate, args.seed)
-    rep = Server(ex, budget, args.max_inflight).run(stream)
+    ex = GpuExecutor(tuning_cache=args.tuning_cache)
+    cap, poi = serve_mix(ex, args.requests, args.seed, int(args.budget_gib * GIB), args.max_inflight, args.load,
+                         args.rate)
     ex.close()
-    s = rep.summary()
-    s.update(phase="poisson", rate_rps=rate, budget_gib=args.budget_gib, max_inflight=args.max_inflight)
-    print(json.dumps(s), flush=True)
+    for s in (cap, poi):
+        if s is not None:
+            print(json.dumps(s), flush=True)
     return 0
 
 

@@ -285,6 +285,7 @@ class Request:
     n_views: int
     dtype: str  # "f32" | "f16" | "bf16"
     phantom_seed: int
+    cancel_s: float = None  # the client withdraws the request at this time (None: never)
 
 
 def poisson_requests(n: int, rate_per_s: float, seed: int,

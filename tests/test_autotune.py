@@ -50,3 +50,64 @@ def test_split_and_direct_candidates():
     fused = [c for c in cands if c.path == "fused"]
     assert {(c.tap_split, c.direct_taps) for c in fused} == {(-1, False), (0, False), (4, False), (-1, True)}
     assert len({c.key() for c in cands}) == len(cands)  # keys are unique
+
+
+class _FakeCtx:
+    """Records what the tuner applies (the context methods it calls)."""
+
+    def __init__(self, dtype="f32", W=1248, H=960):
+        self.dtype, self.det_width, self.det_height = dtype, W, H
+        self.applied = []
+
+    def set_tuning(self, path, k, zu, tx):
+        self.applied.append(("tuning", path, k, zu, tx))
+
+    def set_options(self, **kw):
+        self.applied.append(("options", tuple(sorted(kw.items()))))
+
+    def set_tap_split(self, split):
+        self.applied.append(("split", split))
+
+
+class _Shape:
+    def __init__(self, *shape):
+        self.shape = shape
+
+
+def test_ensure_tuned_searches_once_then_reads_the_cache(tmp_path):
+    path = str(tmp_path / "cache.json")
+    cands = [at.Candidate("fused", 32, 8, 16), at.Candidate("fused", 64, 8, 16)]
+    times = {at.AUTO.key(): 5.0, cands[0].key(): 4.0, cands[1].key(): 3.0}
+    calls = []
+
+    def fake(c):
+        calls.append(c.key())
+        return times[c.key()]
+
+    ctx = _FakeCtx()
+    vol, proj = _Shape(512, 512, 512), _Shape(496, 960, 1248)
+    best, info = at.ensure_tuned(ctx, vol, proj, None, 0.5, (0, 0, 0), cands=cands, cache_path=path,
+                                 device_name="dev", time_fn=fake)
+    assert best == cands[1] and info["source"] == "search"
+    assert at.AUTO.key() in calls  # the library's own choice is always timed
+    assert info["auto_ms"] == 5.0 and info["best_ms"] == 3.0
+    assert ctx.applied[-3:] == [("tuning", "fused", 64, 8, 16), ("options", (("direct_taps", False),)),
+                                ("split", -1)]
+    n = len(calls)
+    best2, info2 = at.ensure_tuned(_FakeCtx(), vol, proj, None, 0.5, (0, 0, 0), cands=cands, cache_path=path,
+                                   device_name="dev", time_fn=fake)
+    assert best2 == best and info2["source"] == "cache" and len(calls) == n
+    # another device or shape misses the cache
+    _, info3 = at.ensure_tuned(_FakeCtx(), vol, proj, None, 0.5, (0, 0, 0), cands=cands, cache_path=path,
+                               device_name="dev2", time_fn=fake)
+    assert info3["source"] == "search"
+
+
+def test_lookup_and_apply_falls_back_to_the_library_choice(tmp_path):
+    path = str(tmp_path / "cache.json")
+    ctx = _FakeCtx("f16")
+    assert at.lookup_and_apply(ctx, (128, 128, 128), 124, "dev", path) == at.AUTO
+    assert ctx.applied[0] == ("tuning", "auto", 0, 0, 0)
+    key = at.problem_of(ctx, (128, 128, 128), 124).key("dev")
+    at.store(key, at.Result(at.Candidate("fused_direct", 32, 8, 16)), path)
+    assert at.lookup_and_apply(ctx, (128, 128, 128), 124, "dev", path) == at.Candidate("fused_direct", 32, 8, 16)

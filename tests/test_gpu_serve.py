@@ -46,3 +46,21 @@ def test_fast_generator_matches_the_torch_generator():
     fa = synth.filtered_projections(sc, ph, device=dev)
     fb = synth.filtered_projections(sc, ph, device=dev, fast=True)
     assert float((fa - fb).abs().max()) <= 1e-6 * float(fa.abs().max())
+
+
+def test_cancelled_request_on_the_device():
+    """A request withdrawn while its work is on the GPU: its result is dropped, its context and
+    memory come back, and the others finish with the results they have alone."""
+    kw = dict(keep_results=True, scanner_fn=small_scanner, volume_fn=small_volume)
+    reqs = [synth.Request(0, 0.0, 48, 24, "f32", 100000),
+            synth.Request(1, 0.0, 64, 36, "f32", 100001, cancel_s=1e-4),
+            synth.Request(2, 0.0, 32, 12, "f16", 100002)]
+    ex = serve.GpuExecutor(**kw)
+    rep = serve.Server(ex, budget_bytes=8 * serve.GIB, max_inflight=4).run(reqs)
+    assert sorted(c.rid for c in rep.completed) == [0, 2]
+    assert [rid for rid, _, _ in rep.cancelled] == [1]
+    for c in rep.completed:
+        alone = serve.Server(serve.GpuExecutor(**kw), budget_bytes=8 * serve.GIB, max_inflight=1).run(
+            [r for r in reqs if r.rid == c.rid])
+        assert np.array_equal(c.result, alone.completed[0].result)
+    ex.close()

@@ -72,3 +72,50 @@ def test_inflight_limit_is_respected(max_inflight):
     reqs = [synth.Request(i, 0.0, 128, 124, "f32", i) for i in range(7)]
     rep, _ = make(reqs, budget=200 * serve.GIB, max_inflight=max_inflight)
     assert rep.peak_inflight == max_inflight and len(rep.completed) == 7
+
+
+def test_cancelled_requests_leave_the_queue_and_free_their_memory():
+    fp = serve.FakeExecutor(lambda: 0.0).footprint(synth.Request(0, 0.0, 512, 496, "f32", 0))
+    reqs = [synth.Request(0, 0.0, 512, 496, "f32", 0, cancel_s=0.01),  # running when withdrawn
+            synth.Request(1, 0.0, 512, 496, "f32", 1, cancel_s=0.005),  # still waiting: never runs
+            synth.Request(2, 0.0, 512, 496, "f32", 2)]
+    # one fits at a time; each takes 512^3 * 496 / 1e11 = 0.67 s
+    rep, ex = make(reqs, budget=fp + 1)
+    assert [c.rid for c in rep.completed] == [2]
+    how = {rid: where for rid, where, _ in rep.cancelled}
+    assert how == {0: "inflight", 1: "waiting"}
+    assert 1 not in ex.started and ex.discarded == [0]
+    by = {c.rid: c for c in rep.completed}
+    assert by[2].admitted_s < 0.1  # admitted once the cancelled request's memory was freed, not after 0.67 s
+    assert rep.summary()["cancelled"] == 2
+
+
+def test_cancel_from_outside_the_loop():
+    clk = SimClock()
+    ex = serve.FakeExecutor(clk, rate_ups=1e11)
+    srv = serve.Server(ex, 200 * serve.GIB, 8, clock=clk, sleep=clk.sleep)
+    reqs = [synth.Request(i, 0.0, 256, 124, "f32", i) for i in range(3)]
+    srv.cancel(1)
+    rep = srv.run(reqs)
+    assert sorted(c.rid for c in rep.completed) == [0, 2]
+    assert [rid for rid, _, _ in rep.cancelled] == [1]
+
+
+def test_cancel_from_another_thread_while_serving():
+    """Server.cancel from a second thread while run() is going (real clock): the withdrawn request
+    never completes, every other one does."""
+    import threading
+    import time
+
+    ex = serve.FakeExecutor(time.perf_counter, rate_ups=2e10)  # 256^3 x 124 views: ~0.1 s each
+    srv = serve.Server(ex, 200 * serve.GIB, max_inflight=1)
+    reqs = [synth.Request(i, 0.0, 256, 124, "f32", i) for i in range(4)]
+    out = {}
+    t = threading.Thread(target=lambda: out.setdefault("rep", srv.run(reqs)))
+    t.start()
+    time.sleep(0.02)
+    srv.cancel(2)  # still waiting behind requests 0 and 1
+    t.join(timeout=30)
+    rep = out["rep"]
+    assert sorted(c.rid for c in rep.completed) == [0, 1, 3]
+    assert [(rid, where) for rid, where, _ in rep.cancelled] == [(2, "waiting")]

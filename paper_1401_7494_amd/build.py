@@ -20,6 +20,9 @@ SOURCES = ["bp_kernels.hip", "bp_api.cpp", "bp_geometry.cpp", "fdk_kernels.hip",
 # The seeded input generator's GPU kernels: a library of their own, not linked into libbp.so.
 SYNTH_LIB = os.path.join(HERE, "libbpsynth.so")
 SYNTH_SOURCES = ["synth_kernels.hip"]
+# Measured roofs (update bandwidth, copy, VALU rates per instruction class): a library of their own.
+PROBE_LIB = os.path.join(HERE, "libbpprobe.so")
+PROBE_SOURCES = ["probe_kernels.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU ops are disabled for all device code.
@@ -36,6 +39,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     _build_lib(SYNTH_SOURCES, SYNTH_LIB, verbose)
+    _build_lib(PROBE_SOURCES, PROBE_LIB, verbose)
     return _build_lib(SOURCES, LIB, verbose)
 
 

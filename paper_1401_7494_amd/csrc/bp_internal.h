@@ -87,19 +87,30 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 // footprint table from launch_footprint, [tile][view] -- the taps are then
 // staged through LDS.  raw (Layout::Patch with footprints only; else null): the
 // caller's FP32 images of the pass, [n][H][W] -- staged footprints are then
-// copied into LDS as pixels (footprint table made with raw = true).
+// copied into LDS as pixels (footprint table made with raw = true).  poison (LDS-staged passes
+// with z_unroll 8 only): fill the LDS stage with NaN before each staged footprint (testing aid).
+// single_taps (caller's FP32 images): one dword load per tap instead of one 8-byte load per
+// pixel pair.
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
                               const Cull& cull, int xcd_order, const float* inv_scale, const uint2* footprints,
-                              const float* raw, hipStream_t s);
+                              const float* raw, hipStream_t s, bool poison = false, bool single_taps = false);
+
+// Fill `bytes` (a multiple of 4) with copies of a 32-bit word (a kernel, not a memset node).
+hipError_t launch_fill(void* p, size_t bytes, uint32_t word, hipStream_t s);
+// The NaN pattern of the poisoned staging (a quiet NaN as FP32 and as each FP16 half).
+constexpr uint32_t kPoisonPattern = 0x7FC07FC0u;
 
 // Patch records a block of the staged pass holds one view's footprint in (LDS):
 // footprints of up to 64 columns by 32 rows.
 constexpr int kStageRecords = 2048;
 // Footprint table entries {x, y}: y == kFootprintSkip -> the tile misses the
 // detector in that view; y == kFootprintDirect -> read that view's taps
-// directly; otherwise x = cmin | rmin << 16, y = fw | fh << 16.
+// directly; otherwise x = cmin | rmin << 16, y = fw | fh << 16,
+// with the kFootprintInner bit set in y when no position needs clamping into
+// the footprint (fw < 2^15).
 constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
+constexpr uint32_t kFootprintInner = 0x8000u, kFootprintWidthMask = 0x7fffu;
 
 
 // Footprint table of one pass: n views (view constants vc[0, n)), every tile;

@@ -23,9 +23,13 @@
 //     5.1.1): the position is clamped into the bordered frame, so the taps
 //     need no tests, and one 16-byte (8-byte for 16-bit data) record replaces
 //     the four taps.  The record comes either from L1 (an indexed buffer
-//     load) or from the block tile's footprint staged in LDS; the default
-//     pass mixes the two by view.  The plain and direct-fused passes read the
-//     caller's images with per-tap bounds tests instead.
+//     load) or from the block tile's footprint staged in LDS -- for FP32
+//     input the footprint's pixels, each with its right neighbour's
+//     difference, from which an update forms the record; the default pass
+//     mixes the two by view.  Footprints with a record of margin inside the
+//     detector on every side ("interior") need no clamp at all.  The plain
+//     and direct-fused passes read the caller's images with per-tap bounds
+//     tests instead (FP32: each row's pixel pair as one 8-byte load).
 //   * A view whose matrix puts some voxel of the box behind (or too near) the
 //     source plane takes a guarded branch that zeroes such contributions; the
 //     branch is uniform per view, decided once per call.
@@ -33,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "bp_internal.h"
 
@@ -71,23 +77,43 @@ __device__ __forceinline__ float bf16_lo(uint32_t v) { return u32_as_f32(v << 16
 // Tap sources.  Each provides, for one view, the four taps around a position.
 // ---------------------------------------------------------------------------
 
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// Byte-offset buffer load of two FP32 values (the intrinsic itself: the b64 builtin with its
+// elements bit-cast to float compiles to a single dword load here, element 0 used twice).
+__device__ f32x2_t raw_buffer_load_f32x2(i32x4_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+
 // Plain path: the caller's W x H image of T.  Positions are raw detector
 // coordinates; a tap off the detector reads 0 (row and column tests in VALU;
-// every load stays inside the view).
-template <typename T>
+// every load stays inside the view).  PAIRS: FP32 taps of one row as one
+// 8-byte load (W >= 2).
+template <typename T, bool PAIRS = false>
 struct CheckedSource {
     static constexpr uint32_t kElem = sizeof(T);
+    static_assert(!PAIRS || sizeof(T) == 4, "pair taps are FP32");
     const uint8_t* base;
     int W, H;
 
     struct View {
-        __amdgpu_buffer_rsrc_t rs;
+        __amdgpu_buffer_rsrc_t rs;  // single taps
+        i32x4_t pair_rs;            // pair taps: the same raw buffer
     };
 
     __device__ __forceinline__ View view(int k) const
     {
         const uint32_t bytes = (uint32_t)W * (uint32_t)H * kElem;
-        return View{make_rsrc(base + (size_t)k * bytes, bytes)};
+        View v;
+        if constexpr (PAIRS) {
+            const uint64_t a = (uint64_t)(base + (size_t)k * bytes);
+            v.pair_rs.x = (int)(uint32_t)a;
+            v.pair_rs.y = (int)((uint32_t)(a >> 32) & 0xffffu);  // stride 0: byte-addressed
+            v.pair_rs.z = (int)bytes;
+            v.pair_rs.w = 0x00020000;
+        } else {
+            v.rs = make_rsrc(base + (size_t)k * bytes, bytes);
+        }
+        return v;
     }
 
     __device__ __forceinline__ float tap(const View& v, int idx) const
@@ -104,14 +130,27 @@ struct CheckedSource {
 
     // Taps (i0, j) and (i0+1, j) of row j, 0 off the detector.  Indices are
     // clamped into the image before loading, so every load is in bounds.
+    // FP32 with PAIRS (W >= 2): one 8-byte load of the pixel pair at columns
+    // c, c + 1 with c = i0 clamped into [0, W - 2] -- both inside the row, so the
+    // load never reaches past the view's last pixel -- from which the two taps
+    // are picked (i0 = -1: (0, pixel 0); i0 = W - 1: (pixel W - 1, 0)).
     __device__ __forceinline__ void taps_row(const View& v, int i0, int j, float& a, float& b) const
     {
-        const bool c0 = i0 >= 0, c1 = i0 + 1 < W, rj = (j >= 0) & (j < H);
+        const bool rj = (j >= 0) & (j < H);
         const int row = min(max(j, 0), H - 1) * W;
-        const float ta = tap(v, row + max(i0, 0));
-        const float tb = tap(v, row + min(i0 + 1, W - 1));
-        a = (rj & c0) ? ta : 0.0f;
-        b = (rj & c1) ? tb : 0.0f;
+        if constexpr (PAIRS) {
+            const int c = min(max(i0, 0), W - 2);
+            const f32x2_t q = raw_buffer_load_f32x2(v.pair_rs, (row + c) * (int)kElem, 0, 0);
+            const bool left = i0 < 0, right = i0 > W - 2;
+            a = (rj & !left) ? (right ? q.y : q.x) : 0.0f;
+            b = (rj & !right) ? (left ? q.x : q.y) : 0.0f;
+        } else {
+            const bool c0 = i0 >= 0, c1 = i0 + 1 < W;
+            const float ta = tap(v, row + max(i0, 0));
+            const float tb = tap(v, row + min(i0 + 1, W - 1));
+            a = (rj & c0) ? ta : 0.0f;
+            b = (rj & c1) ? tb : 0.0f;
+        }
     }
 
     // Contribution of one view at (u, v, w); 0 unless w > 0 and the position
@@ -144,7 +183,6 @@ struct CheckedSource {
 // so B = a + fx dx + fy (dy + fx dxy): one 16-byte load and three FMAs per
 // voxel update instead of four taps and three lerps.  The coefficients are
 // FP32 whatever the storage type of the projections.
-typedef int i32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 // Indexed buffer load: address = base + vindex * stride; vindex >= num_records reads 0.
@@ -153,6 +191,14 @@ __device__ f32x4_t struct_buffer_load_f32x4(i32x4_t rsrc, int vindex, int voffse
 // Byte-offset buffer load of one FP32 value; offsets >= num_records read 0.
 __device__ float raw_buffer_load_f32(i32x4_t rsrc, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.raw.buffer.load.f32");
+
+// med3 clamp of a position into [lo, hi], or the position itself where it is known to lie there.
+template <bool CLAMP>
+__device__ __forceinline__ float clamp_to(float x, float lo, float hi)
+{
+    if constexpr (CLAMP) return __builtin_amdgcn_fmed3f(x, lo, hi);
+    else return x;
+}
 
 struct PatchSource {
     const uint8_t* base;
@@ -209,12 +255,14 @@ struct PatchSource {
 
     // Column view (u and w do not depend on z): everything but the row is
     // shared by the ZU voxels of the thread's column.  t(Z) = (v_xy + P[1][2] Z) / w + 1.
-    template <int ZU>
+    // CLAMP = false: the caller knows every position lies inside the bordered frame (an interior
+    // footprint), so the clamps are left out.
+    template <int ZU, bool CLAMP = true>
     __device__ __forceinline__ void column(const View& vw, float uxy, float vxy, float wxy, float p12,
                                            const float (&Z)[ZU], float (&acc)[ZU]) const
     {
         const float r = __builtin_amdgcn_rcpf(wxy);
-        const float s = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
+        const float s = clamp_to<CLAMP>(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
         const int c0 = (int)s;
         const float fx = __builtin_amdgcn_fractf(s);
         const float r2 = r * r;
@@ -222,7 +270,7 @@ struct PatchSource {
         const float tb = fmaf(vxy, r, 1.0f);
 #pragma unroll
         for (int i = 0; i < ZU; ++i) {
-            const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
+            const float t = clamp_to<CLAMP>(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
             acc[i] = fmaf(patch_at(vw, c0, fx, t), r2, acc[i]);
         }
     }
@@ -231,11 +279,12 @@ struct PatchSource {
     // position is clamped into the bordered frame [0, W+1] x [0, H+1]; a
     // clamped position lands on border patches whose value there is exactly 0,
     // as the zero-extended image would give.
+    template <bool CLAMP = true>
     __device__ __forceinline__ float contrib_safe(const View& vw, float u, float v, float w) const
     {
         const float r = __builtin_amdgcn_rcpf(w);
-        const float s = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
-        const float t = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
+        const float s = clamp_to<CLAMP>(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
+        const float t = clamp_to<CLAMP>(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
         return patch(vw, s, t) * (r * r);
     }
 
@@ -253,10 +302,11 @@ struct PatchSource {
 };
 
 // FP32 projections: directly read views take patch records as PatchSource
-// does; a staged footprint is copied into LDS as the caller's FP32 pixels (a
-// quarter of the bytes of its records), and each update forms its patch's
-// coefficients from the four pixels with the same FP32 operations as
-// patch_kernel, so both paths give the same bits.
+// does; a staged footprint is loaded as the caller's FP32 pixels (a quarter
+// of the bytes of its records) and goes into LDS as pairs (pixel, difference
+// to its right neighbour), the difference formed across lanes as it is
+// staged; each update forms its patch's coefficients from two such pairs with
+// the same FP32 operations as patch_kernel, so both paths give the same bits.
 struct RawPatchSource : PatchSource {
     const float* raw;  // the caller's images of the pass, [n][H][W]
     static constexpr bool kRawStage = true;
@@ -274,17 +324,6 @@ struct RawPatchSource : PatchSource {
         return rs;
     }
 
-    // The record of patch (r, c) from the pixels (r, c), (r, c+1), (r+1, c), (r+1, c+1).
-    static __device__ __forceinline__ Rec record(float a, float b, float cc, float d)
-    {
-        const float dx = b - a;
-        Rec q;
-        q.x = a;
-        q.y = dx;
-        q.z = cc - a;
-        q.w = (d - cc) - dx;
-        return q;
-    }
 };
 
 // Compact bilinear-patch layout for 16-bit projections: the same four
@@ -351,12 +390,14 @@ struct Patch16Source {
         return patch_at(vw, (int)s, __builtin_amdgcn_fractf(s), t);
     }
 
-    template <int ZU>
+    // CLAMP = false: the caller knows every position lies inside the bordered frame (an interior
+    // footprint), so the clamps are left out.
+    template <int ZU, bool CLAMP = true>
     __device__ __forceinline__ void column(const View& vw, float uxy, float vxy, float wxy, float p12,
                                            const float (&Z)[ZU], float (&acc)[ZU]) const
     {
         const float r = __builtin_amdgcn_rcpf(wxy);
-        const float s = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
+        const float s = clamp_to<CLAMP>(fmaf(uxy, r, 1.0f), 0.0f, (float)(W + 1));
         const int c0 = (int)s;
         const float fx = __builtin_amdgcn_fractf(s);
         const float r2 = weight_column(vw, r);
@@ -364,16 +405,17 @@ struct Patch16Source {
         const float tb = fmaf(vxy, r, 1.0f);
 #pragma unroll
         for (int i = 0; i < ZU; ++i) {
-            const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
+            const float t = clamp_to<CLAMP>(fmaf(Z[i], dt, tb), 0.0f, (float)(H + 1));
             acc[i] = fmaf(patch_at(vw, c0, fx, t), r2, acc[i]);
         }
     }
 
+    template <bool CLAMP = true>
     __device__ __forceinline__ float contrib_safe(const View& vw, float u, float v, float w) const
     {
         const float r = __builtin_amdgcn_rcpf(w);
-        const float s = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
-        const float t = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
+        const float s = clamp_to<CLAMP>(fmaf(u, r, 1.0f), 0.0f, (float)(W + 1));
+        const float t = clamp_to<CLAMP>(fmaf(v, r, 1.0f), 0.0f, (float)(H + 1));
         return patch(vw, s, t) * weight_voxel(vw, r);
     }
 
@@ -393,6 +435,10 @@ struct Patch16Source {
 // ---------------------------------------------------------------------------
 // The back-projection pass.
 // ---------------------------------------------------------------------------
+template <bool B>
+struct bool_tag {
+    static constexpr bool value = B;
+};
 
 template <class Src>
 struct has_column {
@@ -550,14 +596,31 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
 // ---------------------------------------------------------------------------
 template <class Src, bool RAW = Src::kRawStage>
 struct StageOf {
-    using type = typename Src::Rec;
+    using type = typename Src::Rec;  // what a lane prefetches and what the stage holds: records
 };
 template <class Src>
 struct StageOf<Src, true> {
-    using type = float;
+    using type = f32x2_t;  // the stage: each pixel with its right neighbour's difference
+};
+template <class Src, bool RAW = Src::kRawStage>
+struct PrefetchOf {
+    using type = typename Src::Rec;
+};
+template <class Src>
+struct PrefetchOf<Src, true> {
+    using type = float;  // a lane prefetches pixels
 };
 
-template <class Src, int ZU, int TX>
+// The value of v in lane i + 1 of the wavefront (DPP wave shift; lane 63 gets nothing useful).
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+
+// POISON (a testing aid, instantiated for ZU = 8 only): before each staged footprint is written,
+// every word of the LDS stage is set to a NaN pattern, so that any read of a stage element the
+// footprint did not write would turn the voxel's sum into NaN.
+template <class Src, int ZU, int TX, bool POISON = false>
 __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
     const uint2* __restrict__ fp, int xcd_order)
@@ -565,7 +628,8 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     using Rec = typename Src::Rec;
     constexpr bool kRaw = Src::kRawStage;
     static_assert(kStageMaxWidth * kStageMaxHeight == kStageRecords, "LDS stage shape");
-    using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels
+    using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels with differences
+    using PreT = typename PrefetchOf<Src>::type;
     __shared__ StageT lds[kRaw ? kRawStride * kRawRows : kStageRecords];
     constexpr int TY = kBlock / TX;
     const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
@@ -593,12 +657,12 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     // kStageSlots; FP32 pixels: the fw + 1 columns and fh + 1 rows of the patches' corners,
     // fw < 64 and fh < 4 kRawSlots (the footprint table keeps to these bounds).
     constexpr int kSlots = kRaw ? kRawSlots : kStageSlots;
-    StageT pre[kSlots];
+    PreT pre[kSlots];
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
     auto prefetch = [&](int k, uint2 f) {
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
-        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
+        const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
             // Padded pixel (r, c) is detector pixel (c - 1, r - 1), at byte offset ((r - 1) W + c - 1) 4
             // of the view.  A pixel off the detector is read at an offset past the view's W H 4 < 2^31
@@ -631,13 +695,20 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     };
     auto staged = [](uint2 f) { return f.y != kFootprintSkip && f.y != kFootprintDirect; };
     auto stage = [&](StageT* buf, uint2 f) {  // the prefetched records or pixels into LDS
-        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
+        const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
+            // pixel (r, c) goes in with P(r, c + 1) - P(r, c), the difference patch_kernel forms
+            // (the next lane holds column c + 1; column fw's difference is never read)
             if (lane <= fw) {
                 StageT* dst = buf + wave * kRawStride + lane;
 #pragma unroll
                 for (int j = 0; j < kSlots; ++j)
-                    if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = pre[j];
+                    if (wave + 4 * j <= fh) {
+                        StageT e;
+                        e.x = pre[j];
+                        e.y = from_next_lane(pre[j]) - pre[j];
+                        dst[4 * j * kRawStride] = e;
+                    }
             }
         } else {
             if (lane < fw) {
@@ -653,8 +724,16 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     auto staged_rec = [&](uint32_t off) -> Rec {
         const char* lds_b = reinterpret_cast<const char*>(lds);
         if constexpr (kRaw) {
-            const float* q = static_cast<const float*>(__builtin_assume_aligned(lds_b + off, 4));
-            return RawPatchSource::record(q[0], q[1], q[kRawStride], q[kRawStride + 1]);
+            // rows r0 and r0 + 1: (a, b - a) and (c, d - c); the record (a, dx, dy, dxy) with the
+            // roundings of patch_kernel: dy = c - a, dxy = (d - c) - dx
+            const StageT* q = static_cast<const StageT*>(__builtin_assume_aligned(lds_b + off, 8));
+            const StageT top = q[0], bot = q[kRawStride];
+            Rec r;
+            r.x = top.x;
+            r.y = top.y;
+            r.z = bot.x - top.x;
+            r.w = bot.y - top.y;
+            return r;
         } else {
             return *static_cast<const Rec*>(__builtin_assume_aligned(lds_b + off, sizeof(Rec)));
         }
@@ -668,6 +747,11 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         const uint2 f = f_next;  // the same for the whole block
         if (staged(f)) {
             __syncthreads();  // every wave is done with the previous footprint
+            if constexpr (POISON) {
+                uint32_t* words = reinterpret_cast<uint32_t*>(lds);
+                for (int i = (int)threadIdx.x; i < (int)(sizeof(lds) / 4); i += kBlock) words[i] = kPoisonPattern;
+                __syncthreads();
+            }
             stage(lds, f);
             __syncthreads();
         }
@@ -682,6 +766,8 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
         const float vxy = fmaf(c.p[5], Y, fmaf(c.p[4], X, c.p[7]));
         const float wxy = fmaf(c.p[9], Y, fmaf(c.p[8], X, c.p[11]));
         if (f.y == kFootprintDirect) {
+            // directly read views keep the clamp into the bordered frame (without it the compiler
+            // keeps all ZU record loads in flight at once: 114 VGPRs instead of 94, measured)
             if (c.mode == kModeColumn) {
                 src.column(view, uxy, vxy, wxy, c.p[6], Z, acc);
             } else if (c.mode == kModeSafe) {
@@ -698,48 +784,60 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             continue;
         }
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
-        const int fw = (int)(f.y & 0xffffu), fh = (int)(f.y >> 16);
-        // positions are clamped into [cmin, cmin + fw) x [rmin, rmin + fh) (the upper bounds the
-        // largest floats below them): a position inside keeps its fraction, and the patch stays in
-        // the footprint
-        const float s_lo = (float)cmin, s_hi = __int_as_float(__float_as_int((float)(cmin + fw)) - 1);
-        const float t_lo = (float)rmin, t_hi = __int_as_float(__float_as_int((float)(rmin + fh)) - 1);
+        const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         // byte offsets of the stage, so that a row's address is one 24-bit multiply-add:
         // patch (r0, c0) at r0 * row_b + (c0 - cmin - rmin * stride) * elem
         const int stride = kRaw ? kRawStride : fw;
         const uint32_t elem = (uint32_t)sizeof(StageT);
         const uint32_t row_b = (uint32_t)stride * elem;
         const int base = -(rmin * stride + cmin);
-        if (c.mode == kModeColumn) {
-            const float r = __builtin_amdgcn_rcpf(wxy);
-            const float sc = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), s_lo, s_hi);
-            const int c0 = (int)sc;
-            const float fx = __builtin_amdgcn_fractf(sc);
-            const float r2 = src.weight_column(view, r);
-            const float dt = c.p[6] * r;
-            const float tb = fmaf(vxy, r, 1.0f);
-            const uint32_t cb_b = (uint32_t)(base + c0) * elem;
-#pragma unroll
-            for (int i = 0; i < ZU; ++i) {
-                const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), t_lo, t_hi);
-                const int r0 = (int)t;
-                const float fy = __builtin_amdgcn_fractf(t);
-                const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + cb_b);
-                acc[i] = fmaf(Src::eval(q, fx, fy), r2, acc[i]);
+        // positions are clamped into [cmin, cmin + fw) x [rmin, rmin + fh) (the upper bounds the
+        // largest floats below them): a position inside keeps its fraction, and the patch stays in
+        // the footprint.  An interior footprint (kFootprintInner) has a record of margin on every
+        // side of every position of the tile and needs no clamp.
+        auto staged_view = [&](auto clamp_tag) {
+            constexpr bool CLAMP = decltype(clamp_tag)::value;
+            float s_lo = 0.0f, s_hi = 0.0f, t_lo = 0.0f, t_hi = 0.0f;
+            if constexpr (CLAMP) {
+                s_lo = (float)cmin;
+                s_hi = __int_as_float(__float_as_int((float)(cmin + fw)) - 1);
+                t_lo = (float)rmin;
+                t_hi = __int_as_float(__float_as_int((float)(rmin + fh)) - 1);
             }
-        } else {  // safe
+            if (c.mode == kModeColumn) {
+                const float r = __builtin_amdgcn_rcpf(wxy);
+                const float sc = clamp_to<CLAMP>(fmaf(uxy, r, 1.0f), s_lo, s_hi);
+                const int c0 = (int)sc;
+                const float fx = __builtin_amdgcn_fractf(sc);
+                const float r2 = src.weight_column(view, r);
+                const float dt = c.p[6] * r;
+                const float tb = fmaf(vxy, r, 1.0f);
+                const uint32_t cb_b = (uint32_t)(base + c0) * elem;
 #pragma unroll
-            for (int i = 0; i < ZU; ++i) {
-                const float u = fmaf(c.p[2], Z[i], uxy), v = fmaf(c.p[6], Z[i], vxy), w = fmaf(c.p[10], Z[i], wxy);
-                const float r = __builtin_amdgcn_rcpf(w);
-                const float sv = __builtin_amdgcn_fmed3f(fmaf(u, r, 1.0f), s_lo, s_hi);
-                const float tv = __builtin_amdgcn_fmed3f(fmaf(v, r, 1.0f), t_lo, t_hi);
-                const int c0 = (int)sv, r0 = (int)tv;
-                const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + (uint32_t)(base + c0) * elem);
-                const float val = Src::eval(q, __builtin_amdgcn_fractf(sv), __builtin_amdgcn_fractf(tv));
-                acc[i] += val * src.weight_voxel(view, r);
+                for (int i = 0; i < ZU; ++i) {
+                    const float t = clamp_to<CLAMP>(fmaf(Z[i], dt, tb), t_lo, t_hi);
+                    const int r0 = (int)t;
+                    const float fy = __builtin_amdgcn_fractf(t);
+                    const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + cb_b);
+                    acc[i] = fmaf(Src::eval(q, fx, fy), r2, acc[i]);
+                }
+            } else {  // safe
+#pragma unroll
+                for (int i = 0; i < ZU; ++i) {
+                    const float u = fmaf(c.p[2], Z[i], uxy), v = fmaf(c.p[6], Z[i], vxy),
+                                w = fmaf(c.p[10], Z[i], wxy);
+                    const float r = __builtin_amdgcn_rcpf(w);
+                    const float sv = clamp_to<CLAMP>(fmaf(u, r, 1.0f), s_lo, s_hi);
+                    const float tv = clamp_to<CLAMP>(fmaf(v, r, 1.0f), t_lo, t_hi);
+                    const int c0 = (int)sv, r0 = (int)tv;
+                    const Rec q = staged_rec(__umul24((uint32_t)r0, row_b) + (uint32_t)(base + c0) * elem);
+                    const float val = Src::eval(q, __builtin_amdgcn_fractf(sv), __builtin_amdgcn_fractf(tv));
+                    acc[i] += val * src.weight_voxel(view, r);
+                }
             }
-        }
+        };
+        if (f.y & kFootprintInner) staged_view(bool_tag<false>{});
+        else staged_view(bool_tag<true>{});
     }
 
     if (in_xy) {
@@ -768,8 +866,9 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // guarded view, a footprint wider than max_w records, taller than max_h or
 // of more than `cap` records, or one of the views k with
 // k % 8 < direct_eighths -- those read their taps directly, so that the
-// pass draws on the L1 path and the LDS path at once.  One thread per
-// (tile, view).
+// pass draws on the L1 path and the LDS path at once.  The kFootprintInner
+// bit of a staged entry's width field marks an interior footprint, whose
+// positions need no clamp.  One thread per (tile, view).
 // ---------------------------------------------------------------------------
 __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
                                  int gx, int gy, int n_tiles, int W, int H, int cap, int max_w, int max_h,
@@ -788,7 +887,7 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
     const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
     bool left = true, right = true, top = true, bottom = true;
-    double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0;
+    double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0, err = 0.0;
     for (int q = 0; q < 8; ++q) {
         const double X = (double)box.ox + (double)box.vs * xs[q & 1];
         const double Y = (double)box.oy + (double)box.vs * ys[(q >> 1) & 1];
@@ -805,11 +904,26 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
         smax = q ? fmax(smax, s) : s;
         tmin = q ? fmin(tmin, t) : t;
         tmax = q ? fmax(tmax, t) : t;
+        // first-order bound on the FP32 error of the pass's position (each FP32 operation rounds by
+        // at most 2^-24 of its result; the reciprocal by 2^-23): 8 roundings on the magnitudes
+        // of the terms of u (v) and of w, plus the +1 of the padded coordinate
+        const double au = fabs((double)c.p[0] * X) + fabs((double)c.p[1] * Y) + fabs((double)c.p[2] * Z) + fabs((double)c.p[3]);
+        const double av = fabs((double)c.p[4] * X) + fabs((double)c.p[5] * Y) + fabs((double)c.p[6] * Z) + fabs((double)c.p[7]);
+        const double aw = fabs((double)c.p[8] * X) + fabs((double)c.p[9] * Y) + fabs((double)c.p[10] * Z) + fabs((double)c.p[11]);
+        const double g = 8.0 * 0x1p-24;
+        const double es = g * (au + fabs(s - 1.0) * aw) / fabs(w) + 0x1p-23 * (2.0 * fabs(s) + 2.0);
+        const double et = g * (av + fabs(t - 1.0) * aw) / fabs(w) + 0x1p-23 * (2.0 * fabs(t) + 2.0);
+        err = fmax(err, fmax(es, et));
     }
     if (left | right | top | bottom) {
         out[id] = make_uint2(0u, kFootprintSkip);
         return;
     }
+    // Interior: the rectangle below (one record of margin on each side of the corners' range) lies
+    // inside the bordered frame without cutting, and the FP32 position error of the pass is far
+    // below that margin, so no position of the tile needs clamping.  (NaN compares false.)
+    const bool inner = err < 0.25 && floor(smin) - 1.0 >= 0.0 && floor(smax) + 1.0 <= (double)(W + 1) &&
+                       floor(tmin) - 1.0 >= 0.0 && floor(tmax) + 1.0 <= (double)(H + 1);
     if ((k & 7) < direct_eighths) {  // this share of the views reads its taps directly (through L1)
         out[id] = make_uint2(0u, kFootprintDirect);
         return;
@@ -825,13 +939,20 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
         if (big) big[k] = 1u;  // this view's records are read after all (every writer stores 1)
         return;
     }
-    out[id] = make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16), (uint32_t)fw | ((uint32_t)fh << 16));
+    out[id] = make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16),
+                         (uint32_t)fw | (inner ? kFootprintInner : 0u) | ((uint32_t)fh << 16));
 }
 
 __global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) p[i] = 0u;
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t word)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = word;
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,7 +1167,7 @@ hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, in
 
 template <class Src, int TX>
 hipError_t launch_zu_lds(int zu, float* vol, const Box& box, const ViewConst* vc, int n, const Src& src,
-                         const uint2* fp, int xcd_order, hipStream_t s)
+                         const uint2* fp, int xcd_order, bool poison, hipStream_t s)
 {
     if (xcd_order >= 2) {
         const int ax = xcd_order >> 1, ay = kXcds / ax;
@@ -1061,6 +1182,12 @@ hipError_t launch_zu_lds(int zu, float* vol, const Box& box, const ViewConst* vc
 #define BP_LAUNCH(Z)                                                                                     \
     hipLaunchKernelGGL((backproject_lds_kernel<Src, Z, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, fp, \
                        xcd_order)
+    if (poison) {
+        if (zu != 8) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((backproject_lds_kernel<Src, 8, TX, true>), grid(8), block, 0, s, vol, box, vc, n, src, fp,
+                           xcd_order);
+        return hipGetLastError();
+    }
     switch (zu) {
     case 1: BP_LAUNCH(1); break;
     case 2: BP_LAUNCH(2); break;
@@ -1100,6 +1227,14 @@ hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* o
         hipLaunchKernelGGL(patch_kernel<uint16_t>, grid, block, 0, s, (const uint16_t*)proj, W, H, q, need);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void* p, size_t bytes, uint32_t word, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    if (n) hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, n, word);
     return hipGetLastError();
 }
 
@@ -1167,7 +1302,7 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
                               int xcd_order, const float* inv_scale, const uint2* fp, const float* raw,
-                              hipStream_t s)
+                              hipStream_t s, bool poison, bool single_taps)
 {
     const uint8_t* base = (const uint8_t*)src;
     if (fp && raw && layout == Layout::Patch) {
@@ -1177,10 +1312,10 @@ hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float
         ps.H = H;
         ps.raw = raw;
         switch (tile_x) {
-        case 64: return launch_zu_lds<RawPatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 32: return launch_zu_lds<RawPatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 16: return launch_zu_lds<RawPatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 8: return launch_zu_lds<RawPatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 64: return launch_zu_lds<RawPatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 32: return launch_zu_lds<RawPatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 16: return launch_zu_lds<RawPatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 8: return launch_zu_lds<RawPatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1188,20 +1323,20 @@ hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float
     if (fp && layout == Layout::Patch16) {
         const Patch16Source ps{base, W, H, inv_scale};
         switch (tile_x) {
-        case 64: return launch_zu_lds<Patch16Source, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 32: return launch_zu_lds<Patch16Source, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 16: return launch_zu_lds<Patch16Source, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 8: return launch_zu_lds<Patch16Source, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 64: return launch_zu_lds<Patch16Source, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 32: return launch_zu_lds<Patch16Source, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 16: return launch_zu_lds<Patch16Source, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 8: return launch_zu_lds<Patch16Source, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (fp && layout == Layout::Patch) {
         const PatchSource ps{base, W, H};
         switch (tile_x) {
-        case 64: return launch_zu_lds<PatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 32: return launch_zu_lds<PatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 16: return launch_zu_lds<PatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
-        case 8: return launch_zu_lds<PatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, s);
+        case 64: return launch_zu_lds<PatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 32: return launch_zu_lds<PatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 16: return launch_zu_lds<PatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+        case 8: return launch_zu_lds<PatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -1227,12 +1362,12 @@ hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float
         }
     }
     {
-#define BP_CHECKED(T)                                                                                           \
-    (tile_x == 16 ? launch_zu<CheckedSource<T>, false, 16>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s)  \
-                  : launch_zu<CheckedSource<T>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s))
+#define BP_CHECKED(...)                                                                                         \
+    (tile_x == 16 ? launch_zu<CheckedSource<__VA_ARGS__>, false, 16>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s) \
+                  : launch_zu<CheckedSource<__VA_ARGS__>, false, 64>(zu, vol, box, vc, n, {base, W, H}, cl, xcd_order, s))
         if (tile_x != 16 && tile_x != 64) return hipErrorInvalidValue;
         switch (dt) {
-        case Dtype::F32: return BP_CHECKED(float);
+        case Dtype::F32: return single_taps || W < 2 ? BP_CHECKED(float, false) : BP_CHECKED(float, true);
         case Dtype::F16: return BP_CHECKED(__half);
         case Dtype::BF16: return BP_CHECKED(uint16_t);
         }

@@ -208,7 +208,7 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_set_tuning(h, 9, 0, 0, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 3, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_options(h, 1 << 13) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 1 << 15) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_options(h, 3 << 5) == bp.BP_ERR_INVALID_ARG  # region split of 3 along x
         assert L.bp_set_options(h, (1 << 10) | (1 << 11)) == bp.BP_ERR_INVALID_ARG  # serial and overlapped
         torch.cuda.synchronize()
@@ -362,9 +362,44 @@ def test_parity_l512_sampled(dtype, compact, path):
             assert e["max_abs_over_max"] <= max_tol, (name, e)
 
 
+def tilted(P64, deg):
+    """The orbit tilted by ``deg`` degrees about the x axis (P T, T the rotation of the world frame),
+    composed in FP64 and rounded once to FP32: every view has P[0][2] and P[2][2] non-zero."""
+    a = np.radians(deg)
+    T = np.eye(4)
+    T[1, 1], T[1, 2], T[2, 1], T[2, 2] = np.cos(a), -np.sin(a), np.sin(a), np.cos(a)
+    return (np.asarray(P64, dtype=np.float64) @ T).astype(np.float32)
+
+
+def test_parity_l512_tilted_orbit_sampled():
+    """The L=512 workload through a tilted orbit (7 degrees about x): no view takes the column
+    branch, every update runs Part 1 per voxel (the general branch), in the library's automatic
+    configuration; every 8th voxel per axis against the oracle, and the centre block."""
+    wl = synth.WORKLOADS["fdk_l512_v496_f32"]
+    v = wl.volume
+    proj = gc.full_projections(wl.phantom_seed)
+    P64, _ = bp.circular_matrices(*wl.scanner.geometry_args())
+    P32 = tilted(P64, 7.0)
+    assert ((P32[:, 0, 2] != 0) & (P32[:, 2, 2] != 0)).mean() > 0.99
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin)
+    proj_np = proj.cpu().numpy()
+    xyz = strided_sample(v.L, 8, 3)
+    ref_s = oracle.backproject_points(proj_np, P32.astype(np.float64), v.voxel_size, v.origin, xyz)
+    err = gc.error_stats(got[xyz[:, 2], xyz[:, 1], xyz[:, 0]], ref_s)
+    print(f"\nL=512 tilted uniform sample: {err}")
+    assert err["rel_l2"] <= gc.REL_L2_TOL, err
+    assert err["max_abs_over_max"] <= gc.MAX_ABS_TOL, err
+    blk = L512_BLOCKS["centre"]
+    (x0, x1), (y0, y1), (z0, z1) = blk
+    ref = gc.run_oracle(proj_np, P32, v.L, v.voxel_size, v.origin, block=blk)
+    e = gc.error_stats(got[z0:z1, y0:y1, x0:x1], ref)
+    print(f"L=512 tilted centre block: {e}")
+    assert e["rel_l2"] <= gc.REL_L2_TOL, e
+
+
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
               order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1,
-              staging="auto", stage_records=False):
+              staging="auto", stage_records=False, poison=False):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
     p = proj.to(dev).contiguous()
@@ -374,11 +409,62 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
         ctx.set_tuning("fused", k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
                         direct_taps=direct_taps, wide_staging=wide_staging, staging=staging,
-                        stage_records=stage_records)
+                        stage_records=stage_records, poison_staging=poison)
         ctx.set_tap_split(tap_split)
         ctx.backproject(vol, p, m, vs, origin)
         torch.cuda.synchronize()
     return vol.cpu().numpy()
+
+
+def _run_direct(proj, P32, shape, vs, origin, path, single_taps, zu=8, tx=16, k=5):
+    dev = torch.device("cuda:0")
+    vol = torch.zeros(shape, dtype=torch.float32, device=dev)
+    p = proj.to(dev).contiguous()
+    m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
+    n, H, W = p.shape
+    with bp.Context(W, H, "f32") as ctx:
+        ctx.set_tuning(path, k, zu, tx)
+        ctx.set_options(single_taps=single_taps)
+        ctx.backproject(vol, p, m, vs, origin)
+        torch.cuda.synchronize()
+    return vol.cpu().numpy()
+
+
+@pytest.mark.parametrize("path", ["plain", "fused_direct"])
+def test_pair_taps_equal_single_taps(path):
+    """On the caller's FP32 images, each row's pixel pair read as one 8-byte load gives the same
+    bits as one dword per tap: boxes across every detector edge and corner (pairs clamped into
+    the row at column 0 and W - 2), views behind the source, a two-column detector."""
+    sc = synth.Scanner(n_views=16, W=96, H=64, pitch=2.0)
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(79))
+    P32 = gc.product_matrices(sc)
+    shape, vs = (24, 40, 40), 2.0
+    o = _box_origin(shape, vs)
+    for shift in ((0.0, 0.0, 0.0), (60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
+        origin = (o[0] + shift[0], o[1] + shift[1], o[2] + shift[2])
+        for zu, tx in ((8, 16), (4, 64)):
+            a = _run_direct(proj, P32, shape, vs, origin, path, True, zu, tx)
+            b = _run_direct(proj, P32, shape, vs, origin, path, False, zu, tx)
+            assert np.array_equal(a, b), (shift, zu, tx)
+            assert np.abs(a).max() > 0
+    ref = _oracle_box(proj, P32, shape, vs, origin)
+    assert gc.rel_l2(b, ref) <= gc.REL_L2_TOL
+    # the source inside the box (guarded contributions)
+    sc2 = synth.Scanner(n_views=13, W=96, H=72, pitch=3.0, sid=60.0, sdd=160.0)
+    P2 = gc.product_matrices(sc2)
+    proj2 = synth.filtered_projections(sc2, synth.random_ellipsoids(1401))
+    o2 = _box_origin(BOX, VS)
+    assert np.array_equal(_run_direct(proj2, P2, BOX, VS, o2, path, True),
+                          _run_direct(proj2, P2, BOX, VS, o2, path, False))
+    # detectors of two columns and of one (single taps, whatever the option)
+    for W in (2, 1):
+        img = synth.uniform_images((3, 5, W), seed=W)
+        P = np.array([[[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1]]] * 3, dtype=np.float32)
+        shp, org = (2, 6, 4), (-1.0, -1.0, 0.0)
+        a = _run_direct(img, P, shp, 0.5, org, path, True, 8, 16, 3)
+        b = _run_direct(img, P, shp, 0.5, org, path, False, 8, 16, 3)
+        assert np.array_equal(a, b)
+        assert gc.rel_l2(a, _oracle_box(img, P, shp, 0.5, org)) <= gc.REL_L2_TOL
 
 
 @pytest.mark.parametrize("zu", [1, 8])
@@ -494,6 +580,36 @@ def test_pixel_stage_at_the_detector_corners():
     ref = _oracle_box(proj.numpy(), P32, shape, vs, origin)
     err = gc.error_stats(b, ref)
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
+
+
+@pytest.mark.parametrize("dtype,wide,records", [("f32", False, False), ("f32", False, True), ("bf16", False, False),
+                                                ("bf16", True, False)])
+def test_poisoned_staging_changes_nothing(dtype, wide, records):
+    """The staging copy of each pass and the LDS stage of each footprint filled with NaN before
+    they are written: the result is finite and bit-identical, so no element the staging did not
+    write is ever read -- records of views only some tiles read directly, unused LDS rows and
+    columns, footprints at the detector's edges, guarded views, footprints too large for the
+    stage; any share of direct views; serial and overlapped staging."""
+    sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(77))
+    if dtype != "f32":
+        proj = proj.to(gc.TORCH_DTYPE[dtype])
+    P32 = gc.product_matrices(sc)
+    cases = [((40, 70, 130), 2.0, (0.0, 0.0, 0.0)),
+             ((24, 40, 40), 2.0, (60.0, 0.0, 43.0)),  # across a detector corner
+             ((9, 33, 65), 9.0, (0.0, 0.0, 0.0)),  # large voxels: footprints beyond the stage
+             ((33, 47, 53), 20.0, (0.0, 0.0, 0.0))]  # the source inside the box: guarded views
+    for shape, vs, shift in cases:
+        o = _box_origin(shape, vs)
+        origin = (o[0] + shift[0], o[1] + shift[1], o[2] + shift[2])
+        for split, staging in ((-1, "serial"), (0, "overlap"), (5, "serial")):
+            kw = dict(dtype=dtype, k=13, zu=8, tx=16, wide_staging=wide, stage_records=records, tap_split=split,
+                      staging=staging)
+            a = _run_opts(proj, P32, shape, vs, origin, **kw)
+            b = _run_opts(proj, P32, shape, vs, origin, poison=True, **kw)
+            assert np.isfinite(b).all(), (shape, split, staging)
+            assert np.array_equal(a, b), (shape, split, staging)
+            assert np.abs(a).max() > 0
 
 
 @pytest.mark.parametrize("dtype,wide", [("f32", False), ("bf16", False), ("bf16", True)])

@@ -195,20 +195,22 @@ class Bench:
             ctx.set_options(**options)
         return ctx
 
-    def tune(self, ctx, vol, proj, P, v, cands, label, **options):
+    def tune(self, ctx, vol, proj, P, v, cands, label, include_auto=True, tag="", **options):
         """The autotuner's launch for this shape (from the cache, or searched and stored), applied."""
         t = time.perf_counter()
         best, info = self.at.ensure_tuned(ctx, vol, proj, P, v.voxel_size, v.origin, cands=cands,
-                                          cache_path=self.cache, device_name=self.dev_name)
+                                          cache_path=self.cache, device_name=self.dev_name,
+                                          include_auto=include_auto, tag=tag)
         if options:
             self.at.apply(ctx, best, **options)
         out = {"source": info["source"], "choice": best.key(), "path": best.path, "views_per_pass": best.views_per_pass,
                "z_unroll": best.z_unroll, "tile_x": best.tile_x, "tap_split": best.tap_split,
                "direct_taps": best.direct_taps}
         if info["source"] == "search":
-            out.update(candidates=len(info["timings_ms"]), auto_ms=round(info["auto_ms"], 3),
-                       tuned_ms=round(info["best_ms"], 3), margin_over_auto=round(info["auto_ms"] / info["best_ms"], 4),
+            out.update(candidates=len(info["timings_ms"]), tuned_ms=round(info["best_ms"], 3),
                        search_s=round(time.perf_counter() - t, 1))
+            if info.get("auto_ms"):
+                out.update(auto_ms=round(info["auto_ms"], 3), margin_over_auto=round(info["auto_ms"] / info["best_ms"], 4))
         log(f"bench: tuned {label}: {out}")
         return best, out
 
@@ -261,6 +263,11 @@ class Bench:
         out += [C("fused", k, 8, 16, -1, True) for k in (64, 128)]
         return out
 
+    def cands_plain(self):
+        """The plain form (one volume pass per view) over its z-unroll and tile width."""
+        C = self.at.Candidate
+        return [C("plain", 1, zu, tx) for zu in (1, 2, 4, 8) for tx in (16, 64)]
+
     def cands_serving(self, L, n):
         C = self.at.Candidate
         out = [C("fused_direct", 64, 8, 16), C("fused_direct", 32, 8, 16), C("fused_direct", 64, 8, 64)]
@@ -298,9 +305,13 @@ def headline(b: Bench, res: dict):
         proj = projs[dt]
         ctx = b.context(sc.W, sc.H, dt)
         tuning = None
-        if path == "fused" and not args.no_tune and not fixed:
+        if path in ("fused", "plain") and not args.no_tune and not fixed:
             scratch = torch.zeros((v.L,) * 3, dtype=torch.float32, device=b.dev)
-            _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_l512(sc.n_views), f"L=512 {dt}")
+            if path == "fused":
+                _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_l512(sc.n_views), f"L=512 {dt}")
+            else:
+                _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_plain(), f"L=512 plain {dt}",
+                                   include_auto=False, tag="plain")
             del scratch
         else:
             ctx.set_tuning(path, args.k, args.zu, args.tx)
@@ -533,7 +544,10 @@ def leg_c1(b: Bench):
         ctx = b.context(sc.W, sc.H, "f32")
         tuning = None
         if path:
-            ctx.set_tuning(path)
+            scratch = torch.zeros((v.L,) * 3, dtype=torch.float32, device=b.dev)
+            _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_plain(), "L=128 plain f32", include_auto=False,
+                               tag="plain")
+            del scratch
         else:
             scratch = torch.zeros((v.L,) * 3, dtype=torch.float32, device=b.dev)
             C = b.at.Candidate

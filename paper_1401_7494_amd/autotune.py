@@ -168,28 +168,31 @@ def problem_of(ctx, volume_shape, n_views) -> Problem:
 
 
 def ensure_tuned(ctx, volume, projections, matrices, voxel_size, origin, cands=None, reps=2, warmup=1,
-                 cache_path: str | None = DEFAULT_CACHE, device_name: str | None = None, time_fn=None):
+                 cache_path: str | None = DEFAULT_CACHE, device_name: str | None = None, time_fn=None,
+                 include_auto: bool = True, tag: str = ""):
     """The tuned launch for this call's shape on this device, applied to ``ctx``.
 
     Reads the cache (key: device name and problem shape); on a miss times ``cands`` (plus the
     library's automatic choice) on the device, stores the result and applies the winner.
     ``volume`` is used as scratch by the search (its contents are left undefined).  Returns
     ``(candidate, info)`` with info = {"source": "cache" | "search", "auto_ms", "best_ms",
-    "timings_ms"} (times only for a search).  ``time_fn`` replaces the device timer (tests)."""
+    "timings_ms"} (times only for a search).  ``time_fn`` replaces the device timer (tests).
+    ``include_auto = False`` searches only ``cands`` (e.g. the launches of one path, such as the
+    plain form's); ``tag`` then keeps such a search apart in the cache."""
     problem = problem_of(ctx, volume.shape, projections.shape[0])
     if device_name is None:
         import torch
 
         device_name = torch.cuda.get_device_name(volume.device)
     dev = device_name
-    key = problem.key(dev)
+    key = problem.key(dev) + (f"|{tag}" if tag else "")
     if cache_path:
         hit = lookup(key, cache_path)
         if hit is not None:
             apply(ctx, hit)
             return hit, {"source": "cache", "key": key}
     cands = list(cands) if cands is not None else candidates(problem)
-    if AUTO not in cands:
+    if include_auto and AUTO not in cands:
         cands.insert(0, AUTO)
     if time_fn is None:
         import torch
@@ -199,7 +202,7 @@ def ensure_tuned(ctx, volume, projections, matrices, voxel_size, origin, cands=N
     if cache_path:
         store(key, res, cache_path)
     apply(ctx, res.best)
-    return res.best, {"source": "search", "key": key, "auto_ms": res.timings_ms[AUTO.key()],
+    return res.best, {"source": "search", "key": key, "auto_ms": res.timings_ms.get(AUTO.key()),
                       "best_ms": res.timings_ms[res.best.key()], "timings_ms": res.timings_ms}
 
 

@@ -24,8 +24,8 @@
 //     need no tests, and one 16-byte (8-byte for 16-bit data) record replaces
 //     the four taps.  The record comes either from L1 (an indexed buffer
 //     load) or from the block tile's footprint staged in LDS -- for FP32
-//     input the footprint's pixels, each with its right neighbour's
-//     difference, from which an update forms the record; the default pass
+//     input the footprint's pixels, from which an update forms the record;
+//     the default pass
 //     mixes the two by view.  Footprints with a record of margin inside the
 //     detector on every side ("interior") need no clamp at all.  The plain
 //     and direct-fused passes read the caller's images with per-tap bounds
@@ -302,11 +302,10 @@ struct PatchSource {
 };
 
 // FP32 projections: directly read views take patch records as PatchSource
-// does; a staged footprint is loaded as the caller's FP32 pixels (a quarter
-// of the bytes of its records) and goes into LDS as pairs (pixel, difference
-// to its right neighbour), the difference formed across lanes as it is
-// staged; each update forms its patch's coefficients from two such pairs with
-// the same FP32 operations as patch_kernel, so both paths give the same bits.
+// does; a staged footprint is copied into LDS as the caller's FP32 pixels (a
+// quarter of the bytes of its records), and each update forms its patch's
+// coefficients from the four pixels with the same FP32 operations as
+// patch_kernel, so both paths give the same bits.
 struct RawPatchSource : PatchSource {
     const float* raw;  // the caller's images of the pass, [n][H][W]
     static constexpr bool kRawStage = true;
@@ -596,26 +595,13 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
 // ---------------------------------------------------------------------------
 template <class Src, bool RAW = Src::kRawStage>
 struct StageOf {
-    using type = typename Src::Rec;  // what a lane prefetches and what the stage holds: records
+    using type = typename Src::Rec;  // what the stage holds: records
 };
 template <class Src>
 struct StageOf<Src, true> {
-    using type = f32x2_t;  // the stage: each pixel with its right neighbour's difference
-};
-template <class Src, bool RAW = Src::kRawStage>
-struct PrefetchOf {
-    using type = typename Src::Rec;
-};
-template <class Src>
-struct PrefetchOf<Src, true> {
-    using type = float;  // a lane prefetches pixels
+    using type = float;  // the stage: the footprint's pixels
 };
 
-// The value of v in lane i + 1 of the wavefront (DPP wave shift; lane 63 gets nothing useful).
-__device__ __forceinline__ float from_next_lane(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
-}
 
 // POISON (a testing aid, instantiated for ZU = 8 only): before each staged footprint is written,
 // every word of the LDS stage is set to a NaN pattern, so that any read of a stage element the
@@ -628,8 +614,8 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     using Rec = typename Src::Rec;
     constexpr bool kRaw = Src::kRawStage;
     static_assert(kStageMaxWidth * kStageMaxHeight == kStageRecords, "LDS stage shape");
-    using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels with differences
-    using PreT = typename PrefetchOf<Src>::type;
+    using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels
+    using PreT = StageT;  // what a lane prefetches
     __shared__ StageT lds[kRaw ? kRawStride * kRawRows : kStageRecords];
     constexpr int TY = kBlock / TX;
     const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
@@ -697,18 +683,11 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     auto stage = [&](StageT* buf, uint2 f) {  // the prefetched records or pixels into LDS
         const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
-            // pixel (r, c) goes in with P(r, c + 1) - P(r, c), the difference patch_kernel forms
-            // (the next lane holds column c + 1; column fw's difference is never read)
             if (lane <= fw) {
                 StageT* dst = buf + wave * kRawStride + lane;
 #pragma unroll
                 for (int j = 0; j < kSlots; ++j)
-                    if (wave + 4 * j <= fh) {
-                        StageT e;
-                        e.x = pre[j];
-                        e.y = from_next_lane(pre[j]) - pre[j];
-                        dst[4 * j * kRawStride] = e;
-                    }
+                    if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = pre[j];
             }
         } else {
             if (lane < fw) {
@@ -724,15 +703,15 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
     auto staged_rec = [&](uint32_t off) -> Rec {
         const char* lds_b = reinterpret_cast<const char*>(lds);
         if constexpr (kRaw) {
-            // rows r0 and r0 + 1: (a, b - a) and (c, d - c); the record (a, dx, dy, dxy) with the
-            // roundings of patch_kernel: dy = c - a, dxy = (d - c) - dx
-            const StageT* q = static_cast<const StageT*>(__builtin_assume_aligned(lds_b + off, 8));
-            const StageT top = q[0], bot = q[kRawStride];
+            // the record (a, dx, dy, dxy) of the four pixels with the roundings of patch_kernel
+            const float* q = static_cast<const float*>(__builtin_assume_aligned(lds_b + off, 4));
+            const float a = q[0], b = q[1], cc = q[kRawStride], d = q[kRawStride + 1];
+            const float dx = b - a;
             Rec r;
-            r.x = top.x;
-            r.y = top.y;
-            r.z = bot.x - top.x;
-            r.w = bot.y - top.y;
+            r.x = a;
+            r.y = dx;
+            r.z = cc - a;
+            r.w = (d - cc) - dx;
             return r;
         } else {
             return *static_cast<const Rec*>(__builtin_assume_aligned(lds_b + off, sizeof(Rec)));

@@ -138,6 +138,26 @@ bp_status bp_backproject_box(bp_ctx ctx, float *volume, int nx, int ny, int nz,
                              const void *projections, const float *matrices, int n_views,
                              float voxel_size, const float origin[3], void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): bp_backproject_box with no allocation at all.  The
+ * arguments, layouts, accumulation and checks are those of bp_backproject_box; the taps are read
+ * from the caller's images (PLAIN when the context's path is PLAIN, else FUSED_DIRECT with the
+ * context's K, z_unroll and tile width, K = 64 when not set), which gives the same bits as
+ * bp_backproject_box on those paths.  Scratch (per-view constants and, when it fits beside
+ * them, the clipping mask) lives in a static device array of 4 MiB that each device the library
+ * runs on holds until the process ends; its address is looked up once per device (at
+ * bp_create, else at this entry's first call on the device).  Limits: n_views <= 65536
+ * (BP_ERR_UNSUPPORTED beyond); a call whose clipping mask does not fit computes every
+ * (tile, view) instead (same bits).  Every call on a device shares that device's array:
+ * calls that overlap on one device race -- serialise them (one stream, or events).  No
+ * hipMalloc, hipFree or allocating library routine is called; timing events
+ * (bp_enable_timing) are not recorded.
+ */
+bp_status bp_backproject_noalloc(bp_ctx ctx, float *volume, int nx, int ny, int nz,
+                                 const void *projections, const float *matrices, int n_views,
+                                 float voxel_size, const float origin[3], void *stream);
+
 /* Override the per-call choices of a context (path, K, z_unroll, tile_x); 0 keeps the tuned value. */
 bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unroll, int tile_x);
 

@@ -57,6 +57,8 @@ SIGNATURES = {
     "bp_backproject": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_float, ctypes.POINTER(_c_float), _vp]),
     "bp_backproject_box": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp, _c_int, _c_float,
                                     ctypes.POINTER(_c_float), _vp]),
+    "bp_backproject_noalloc": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _vp, _vp, _c_int, _c_float,
+                                        ctypes.POINTER(_c_float), _vp]),
     "bp_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
     "bp_set_options": (_c_int, [_vp, _c_int]),
     "bp_set_tap_split": (_c_int, [_vp, _c_int]),

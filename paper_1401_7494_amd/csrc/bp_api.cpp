@@ -49,6 +49,8 @@ struct bp_ctx_s {
     double total_ms[3] = {0, 0, 0};
     long long launches[3] = {0, 0, 0};
     std::vector<hipEvent_t> event_pool;
+    // device address of the allocation-free entry point's static scratch on the context's device
+    void* noalloc = nullptr;
 };
 
 namespace {
@@ -388,6 +390,14 @@ bp_status bp_create(const bp_config* cfg, bp_ctx* out)
     bp_ctx ctx = new (std::nothrow) bp_ctx_s();
     if (!ctx) return BP_ERR_OUT_OF_MEMORY;
     ctx->cfg = *cfg;
+    {
+        // set-up of the allocation-free entry point: the scratch array's address on this device
+        DeviceGuard g(cfg->device);
+        if (!g.ok || bp::noalloc_scratch(cfg->device, &ctx->noalloc) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->noalloc = nullptr;  // looked up again at that entry point's first call
+        }
+    }
     *out = ctx;
     return BP_OK;
 }
@@ -632,6 +642,69 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
                                               (ctx->options & BP_OPT_SINGLE_TAPS) != 0);
             });
         }
+        if (e != hipSuccess)
+            return fail(ctx, BP_ERR_LAUNCH, std::string("back-projection kernel: ") + hipGetErrorString(e));
+    }
+    return BP_OK;
+}
+
+bp_status bp_backproject_noalloc(bp_ctx ctx, float* volume, int nx, int ny, int nz, const void* projections,
+                                 const float* matrices, int n_views, float voxel_size, const float origin[3],
+                                 void* stream)
+{
+    if (!ctx) return BP_ERR_INVALID_ARG;
+    if (const bp_status st = check_call(ctx, volume, nx, ny, nz, projections, matrices, n_views, voxel_size, origin))
+        return st;
+    const size_t views_bytes = sizeof(bp::ViewConst) * (size_t)n_views;
+    if (views_bytes > bp::kNoAllocScratchBytes)
+        return fail(ctx, BP_ERR_UNSUPPORTED, "n_views beyond the allocation-free limit of 65536");
+    // The caller's images only: plain passes stay plain, every other choice runs the fused pass on
+    // the caller's images (no staging copy, so no scratch beyond the view constants and the mask).
+    Plan plan = plan_for(ctx, nx, ny, nz, n_views);
+    if (plan.path != BP_PATH_PLAIN) {
+        plan.path = BP_PATH_FUSED_DIRECT;
+        if (plan.tx != 16) plan.tx = 64;
+        const int k_set = ctx->k_override > 0 ? ctx->k_override : ctx->cfg.views_per_pass;
+        plan.k = k_set > 0 ? (k_set < n_views ? k_set : n_views) : (64 < n_views ? 64 : n_views);
+    }
+    const int W = ctx->cfg.det_width, H = ctx->cfg.det_height;
+    const bp::Box box{nx, ny, nz, voxel_size, origin[0], origin[1], origin[2]};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard g(ctx->cfg.device);
+    if (!g.ok) return fail(ctx, BP_ERR_DEVICE, "cannot select the context's device");
+    if (!ctx->noalloc && bp::noalloc_scratch(ctx->cfg.device, &ctx->noalloc) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BP_ERR_DEVICE, "cannot look up the static scratch of this device");
+    }
+    // scratch: view constants, then (256-byte aligned) the clipping mask when it fits beside them;
+    // without it every (tile, view) is computed, which gives the same bits (skipped pairs add 0)
+    const size_t mask_off = (views_bytes + 255) & ~size_t(255);
+    const int words = bp::cull_words(n_views);
+    const size_t mask_bytes = (size_t)bp::n_tiles(nx, ny, nz, plan.zu, plan.tx) * (size_t)words * 4u;
+    const bool culled = plan.path == BP_PATH_FUSED_DIRECT && !(ctx->options & BP_OPT_NO_CULL) &&
+                        mask_off + mask_bytes <= bp::kNoAllocScratchBytes;
+    bp::ViewConst* vc = static_cast<bp::ViewConst*>(ctx->noalloc);
+    uint32_t* mask = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(ctx->noalloc) + mask_off);
+    const bool column_ok = !(ctx->options & BP_OPT_NO_COLUMN);
+    if (bp::launch_prep_views(matrices, n_views, box, column_ok, vc, s) != hipSuccess)
+        return fail(ctx, BP_ERR_LAUNCH, "view-constant kernel launch failed");
+    bp::Cull cull{nullptr, 0, 0};
+    if (culled) {
+        if (bp::launch_cull(vc, n_views, box, plan.zu, plan.tx, W, H, mask, s) != hipSuccess)
+            return fail(ctx, BP_ERR_LAUNCH, "clipping-mask kernel launch failed");
+        cull.bits = mask;
+        cull.words = words;
+    }
+    const size_t img_bytes = (size_t)W * (size_t)H * elem_bytes(ctx->cfg.proj_dtype);
+    const int xcd_order = tile_order(ctx);
+    const bp::Dtype dt = to_dt(ctx->cfg.proj_dtype);
+    for (int k0 = 0; k0 < n_views; k0 += plan.k) {
+        const int kc = n_views - k0 < plan.k ? n_views - k0 : plan.k;
+        cull.kbase = k0;
+        const void* src = static_cast<const uint8_t*>(projections) + (size_t)k0 * img_bytes;
+        const hipError_t e = bp::launch_backproject(dt, bp::Layout::Checked, plan.zu, plan.tx, volume, box, vc + k0, kc,
+                                                    src, W, H, cull, xcd_order, nullptr, nullptr, nullptr, s, false,
+                                                    (ctx->options & BP_OPT_SINGLE_TAPS) != 0);
         if (e != hipSuccess)
             return fail(ctx, BP_ERR_LAUNCH, std::string("back-projection kernel: ") + hipGetErrorString(e));
     }

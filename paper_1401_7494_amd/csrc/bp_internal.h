@@ -129,6 +129,15 @@ inline long n_tiles(int nx, int ny, int nz, int z_unroll, int tile_x)
     return (long)((nx + tile_x - 1) / tile_x) * ((ny + ty - 1) / ty) * ((nz + z_unroll - 1) / z_unroll);
 }
 
+// Device scratch of the allocation-free entry point: a file-scope static array in the kernel
+// source, one copy per device, held until the process ends.  Its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and kept; host code passes
+// that address, never the array's name.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+// The device address of the scratch array on the current device (`device` is its ordinal).
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // Skip bits for every (tile, view) of a call, cull_words(n_views) words per tile.
 hipError_t launch_cull(const ViewConst* vc, int n_views, const Box& box, int z_unroll, int tile_x, int W, int H,
                        uint32_t* out, hipStream_t s);

@@ -39,6 +39,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "bp_internal.h"
 
@@ -1178,7 +1179,28 @@ hipError_t launch_zu_lds(int zu, float* vol, const Box& box, const ViewConst* vc
     return hipGetLastError();
 }
 
+// Scratch of the allocation-free entry point (per-view constants and the clipping mask of a
+// call).  Every call on a device shares that device's copy; calls that overlap on one device race.
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 }  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr)
+{
+    static std::mutex mu;
+    static void* addr[kNoAllocMaxDevices] = {};
+    if (device < 0 || device >= kNoAllocMaxDevices || !ptr) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_prep_views(const float* mats, int n_views, const Box& box, bool column_ok, ViewConst* out,
                              hipStream_t s)

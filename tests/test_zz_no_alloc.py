@@ -1,0 +1,95 @@
+"""The allocation-free entry point (bp_backproject_noalloc) against bp_backproject_box (GPU).
+
+bp_backproject_noalloc keeps its scratch (per-view constants and the clipping mask) in a static
+device array instead of the context's allocations; it runs the same kernels as the box entry
+with the taps read from the caller's images, so the two give the same bits.  Two calls in a
+row on one device share that array, the second smaller than the first.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import gpu_common as gc
+from paper_1401_7494_amd import bp, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+SC = synth.Scanner(n_views=13, W=96, H=72, pitch=3.0)
+
+
+def _noalloc():
+    return bp.lib().bp_backproject_noalloc  # the C entry itself (argument types from the binding)
+
+
+def _origin(shape, vs):
+    nz, ny, nx = shape
+    return (-(nx - 1) / 2 * vs, -(ny - 1) / 2 * vs, -(nz - 1) / 2 * vs)
+
+
+def _both(ctx, proj, P, shape, vs, origin):
+    """(no-alloc volume, box-entry volume) for the same call on one context."""
+    dev = torch.device("cuda:0")
+    p = proj.to(dev).contiguous()
+    m = torch.as_tensor(np.ascontiguousarray(P, dtype=np.float32)).to(dev)
+    a = torch.zeros(shape, dtype=torch.float32, device=dev)
+    b = torch.zeros(shape, dtype=torch.float32, device=dev)
+    nz, ny, nx = shape
+    o = (ctypes.c_float * 3)(*[float(x) for x in origin])
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = _noalloc()(ctx.handle, a.data_ptr(), nx, ny, nz, p.data_ptr(), m.data_ptr(), p.shape[0], float(vs), o,
+                    stream)
+    assert st == bp.BP_OK, ctx.last_error()
+    ctx.backproject(b, p, m, vs, origin)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), b.cpu().numpy()
+
+
+@pytest.mark.parametrize("path,k,zu,tx", [("fused_direct", 5, 8, 16), ("fused_direct", 13, 4, 64),
+                                          ("plain", 1, 8, 64)])
+def test_noalloc_matches_the_box_entry_twice(path, k, zu, tx):
+    proj = synth.filtered_projections(SC, synth.random_ellipsoids(1401))
+    P = gc.product_matrices(SC)
+    with bp.Context(SC.W, SC.H, "f32") as ctx:
+        ctx.set_tuning(path, k, zu, tx)
+        big, small = (21, 37, 70), (9, 16, 20)
+        a, b = _both(ctx, proj, P, big, 3.0, _origin(big, 3.0))
+        assert np.array_equal(a, b) and np.abs(a).max() > 0
+        a2, b2 = _both(ctx, proj[:5], P[:5], small, 3.0, _origin(small, 3.0))  # the second call: smaller
+        assert np.array_equal(a2, b2) and np.abs(a2).max() > 0
+        ref = gc.run_oracle(proj[:5], P[:5], max(small), 3.0, _origin(small, 3.0),
+                            block=((0, small[2]), (0, small[1]), (0, small[0])))
+        assert gc.rel_l2(a2, ref) <= gc.REL_L2_TOL
+
+
+def test_noalloc_at_l512_without_room_for_the_mask():
+    """At 512^3 and 496 views the clipping mask does not fit beside the view constants: every
+    (tile, view) is computed, with the same bits as the masked box entry."""
+    wl = synth.WORKLOADS["fdk_l512_v496_f32"]
+    v = wl.volume
+    proj = gc.full_projections(wl.phantom_seed)
+    P = gc.product_matrices(wl.scanner)
+    with bp.Context(wl.scanner.W, wl.scanner.H, "f32") as ctx:
+        ctx.set_tuning("fused_direct", 64, 8, 16)
+        a, b = _both(ctx, proj, P, (v.L,) * 3, v.voxel_size, v.origin)
+        assert np.array_equal(a, b)
+        # then a smaller call reusing the same scratch
+        c, d = _both(ctx, proj[:40], P[:40], (64, 96, 128), v.voxel_size, v.origin)
+        assert np.array_equal(c, d) and np.abs(c).max() > 0
+
+
+def test_noalloc_rejects_what_it_cannot_hold():
+    dev = torch.device("cuda:0")
+    with bp.Context(8, 8, "f32") as ctx:
+        n = 65537  # view constants beyond the 4 MiB scratch
+        vol = torch.zeros((2, 2, 2), device=dev)
+        proj = torch.zeros((1, 8, 8), device=dev)
+        mats = torch.zeros((1, 12), device=dev)
+        o = (ctypes.c_float * 3)(0, 0, 0)
+        st = _noalloc()(ctx.handle, vol.data_ptr(), 2, 2, 2, proj.data_ptr(), mats.data_ptr(), n, 1.0, o, None)
+        assert st == bp.BP_ERR_UNSUPPORTED and "65536" in ctx.last_error()
+        st = _noalloc()(ctx.handle, None, 2, 2, 2, proj.data_ptr(), mats.data_ptr(), 1, 1.0, o, None)
+        assert st == bp.BP_ERR_INVALID_ARG
+        torch.cuda.synchronize()
+    assert not vol.any()

@@ -45,6 +45,8 @@ class Completed:
     result: object = None
     ingest_ms: float = None  # device time of the ingest (raw projections + FDK pre-processing)
     bp_ms: float = None      # device time of the back projection
+    gen_ms: float = None     # of the ingest: the generator making the raw projections (the detector's stand-in)
+    fdk_ms: float = None     # of the ingest: the library's FDK pre-processing and zeroing the volume
 
     @property
     def latency_s(self) -> float:
@@ -76,6 +78,9 @@ class Report:
             ing = np.array([c.ingest_ms for c in timed])
             bpm = np.array([c.bp_ms for c in timed])
             dev = {"p50_ingest_ms": float(np.percentile(ing, 50)), "p99_ingest_ms": float(np.percentile(ing, 99)),
+                   "sum_generator_ms": float(sum(c.gen_ms or 0.0 for c in timed)),
+                   "sum_fdk_ms": float(sum(c.fdk_ms or 0.0 for c in timed)),
+                   "sum_backprojection_ms": float(bpm.sum()),
                    "p50_backprojection_ms": float(np.percentile(bpm, 50)),
                    "p99_backprojection_ms": float(np.percentile(bpm, 99)),
                    "backprojection_gups": float(sum(c.updates for c in timed) / (bpm.sum() * 1e-3) / 1e9)}
@@ -166,7 +171,7 @@ class Server:
                 if self.ex.poll(h):
                     res, tm = self.ex.finish(h)
                     done.append(Completed(r.rid, r.arrival_s, adm, self.clock() - t0, self.ex.updates(r), fp, res,
-                                          tm.get("ingest_ms"), tm.get("bp_ms")))
+                                          tm.get("ingest_ms"), tm.get("bp_ms"), tm.get("gen_ms"), tm.get("fdk_ms")))
                     used -= fp
                     del inflight[rid]
                     progressed = True
@@ -330,7 +335,7 @@ class GpuExecutor:
         sc, v = self.scanner_fn(r), self.volume_fn(r)
         tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[r.dtype]
         mats = self._matrices(sc)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         raw = None
         with torch.cuda.stream(stream):
             ev[0].record(stream)
@@ -341,6 +346,7 @@ class GpuExecutor:
                 for a in range(0, sc.n_views, 62):
                     views = list(range(a, min(a + 62, sc.n_views)))
                     raw[a:a + len(views)] = synth.line_integrals_fast(sc, ph, views, self.dev).to(torch.float32)
+                ev[3].record(stream)
                 proj = self._fdk_for(sc).filter(raw, r.dtype, stream=stream)
             else:
                 proj = synth.filtered_projections(sc, ph, device=self.dev, out_dtype=tdt, chunk=62)
@@ -362,6 +368,8 @@ class GpuExecutor:
         h["done"].synchronize()
         ev = h["ev"]
         tm = {"ingest_ms": ev[0].elapsed_time(ev[1]), "bp_ms": ev[1].elapsed_time(ev[2])}
+        if self.fast_inputs:
+            tm.update(gen_ms=ev[0].elapsed_time(ev[3]), fdk_ms=ev[3].elapsed_time(ev[1]))
         out = h["vol"].cpu().numpy() if self.keep else float(h["vol"].double().sum())
         self._free_ctx[h["key"]].append(h["ctx"])
         h.clear()

@@ -205,7 +205,7 @@ class Bench:
             self.at.apply(ctx, best, **options)
         out = {"source": info["source"], "choice": best.key(), "path": best.path, "views_per_pass": best.views_per_pass,
                "z_unroll": best.z_unroll, "tile_x": best.tile_x, "tap_split": best.tap_split,
-               "direct_taps": best.direct_taps}
+               "direct_taps": best.direct_taps, "no_column": best.no_column}
         if info["source"] == "search":
             out.update(candidates=len(info["timings_ms"]), tuned_ms=round(info["best_ms"], 3),
                        search_s=round(time.perf_counter() - t, 1))
@@ -214,32 +214,63 @@ class Bench:
         log(f"bench: tuned {label}: {out}")
         return best, out
 
-    def run(self, ctx, proj, P, v, steps, warmup, shape=None, timing=True):
-        """warmup + steps reconstructions into one volume; returns step times (HIP events), the library's
-        kernel timings over the timed steps, and the volume of one reconstruction."""
+    def run(self, ctx, proj, P, v, steps, warmup, shape=None, timing="inside", graph=False):
+        """warmup + steps reconstructions into one volume; returns the step times (HIP events around
+        each step), the library's per-kernel timings (HIP events around each launch, on the stream
+        of the launch) over the timed steps (``timing="inside"``) or over up to 3 further steps
+        ("after": the timed steps carry no per-launch events; None: no kernel timings), and the
+        volume of one reconstruction.  ``graph``: each step replays one reconstruction captured in
+        a HIP graph (launch costs paid once; kernel timings then come "after")."""
         torch = self.torch
         shape = shape or (v.L,) * 3
         vol = torch.zeros(shape, dtype=torch.float32, device=self.dev)
         stream = torch.cuda.current_stream(self.dev)
-        for _ in range(warmup):
+        for _ in range(max(warmup, 1 if graph else 0)):
             ctx.backproject(vol, proj, P, v.voxel_size, v.origin, stream)
         torch.cuda.synchronize()
+        g = None
+        if graph:
+            g = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream(device=self.dev)
+            cs.wait_stream(stream)
+            with torch.cuda.stream(cs):
+                g.capture_begin()
+                ctx.backproject(vol, proj, P, v.voxel_size, v.origin, cs)
+                g.capture_end()
+            torch.cuda.synchronize()
         vol.zero_()
-        if timing:
+        if graph and timing == "inside":
+            timing = "after"
+        if timing == "inside":
             ctx.enable_timing(True)
         starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         torch.cuda.synchronize()
         for i in range(steps):
             starts[i].record(stream)
-            ctx.backproject(vol, proj, P, v.voxel_size, v.origin, stream)
+            if g is not None:
+                g.replay()
+            else:
+                ctx.backproject(vol, proj, P, v.voxel_size, v.origin, stream)
             ends[i].record(stream)
         torch.cuda.synchronize()
         step_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-        kern = {k: ctx.kernel_timing(k) for k in ("backproject", "pad", "views")} if timing else None
-        if timing:
-            ctx.enable_timing(False)
         vol /= float(steps)
+        kern = None
+        if timing == "inside":
+            kern = {k: ctx.kernel_timing(k) for k in ("backproject", "pad", "views")}
+            kern["reconstructions"] = steps
+            ctx.enable_timing(False)
+        elif timing == "after":
+            scratch = torch.zeros(shape, dtype=torch.float32, device=self.dev)
+            ctx.enable_timing(True)
+            for _ in range(min(steps, 3)):
+                ctx.backproject(scratch, proj, P, v.voxel_size, v.origin, stream)
+            torch.cuda.synchronize()
+            kern = {k: ctx.kernel_timing(k) for k in ("backproject", "pad", "views")}
+            kern["reconstructions"] = min(steps, 3)
+            ctx.enable_timing(False)
+            del scratch
         return step_ms, kern, vol
 
     def plan_of(self, ctx, v, n):
@@ -250,7 +281,7 @@ class Bench:
     # ------------------------------------------------------------------ candidates
     def cands_l512(self, n):
         C = self.at.Candidate
-        out = [C("fused", k, zu, tx, sp) for k in (32, 64, 128) for zu in (4, 8) for tx in (16, 32)
+        out = [C("fused", k, zu, tx, sp) for k in (32, 64, 128) for zu in (4, 8) for tx in (8, 16, 32)
                for sp in (-1, 2, 4, 6)]
         out += [C("fused", k, 8, 16, -1, True) for k in (32, 64)]
         return [c for c in out if c.views_per_pass <= n]
@@ -264,9 +295,10 @@ class Bench:
         return out
 
     def cands_plain(self):
-        """The plain form (one volume pass per view) over its z-unroll and tile width."""
+        """The plain form (one volume pass per view) over its z-unroll, tile width and the column
+        branch (hoisting Part 1 out of the z loop, or not)."""
         C = self.at.Candidate
-        return [C("plain", 1, zu, tx) for zu in (1, 2, 4, 8) for tx in (16, 64)]
+        return [C("plain", 1, zu, tx, -1, False, nc) for zu in (1, 2, 4, 8) for tx in (16, 64) for nc in (False, True)]
 
     def cands_serving(self, L, n):
         C = self.at.Candidate
@@ -378,7 +410,7 @@ def headline(b: Bench, res: dict):
     head = out.get("fused_f32") or next(iter(out.values()))
     ms_bp, n_bp = head["kernels"]["backproject"]
     per_launch_ms = ms_bp / max(n_bp, 1)
-    upl = updates * args.steps / max(n_bp, 1)
+    upl = updates * head["kernels"]["reconstructions"] / max(n_bp, 1)
     tflops = FLOPS_PER_UPDATE * upl / (per_launch_ms * 1e-3) / 1e12
     if head["path"] == "fused" and not head["direct_taps"]:
         kernel = "backproject_lds_kernel"
@@ -556,10 +588,15 @@ def leg_c1(b: Bench):
             _, tuning = b.tune(ctx, scratch, proj, P, v, cands, "L=128 f32")
             del scratch
         plan = b.plan_of(ctx, v, sc.n_views)
-        step_ms, kern, vol = b.run(ctx, proj, P, v, max(args.config_steps, 10), 2)
+        steps = max(args.config_steps, 10)
+        step_ms, kern, vol = b.run(ctx, proj, P, v, steps, 2, timing="after")
+        # the same reconstruction captured once in a HIP graph and replayed (launch costs paid once)
+        g_ms, _, g_vol = b.run(ctx, proj, P, v, steps, 2, timing=None, graph=True)
         ctx.close()
         out[name] = {**plan, **stats(step_ms, updates), "tuning": tuning,
-                     "backproject_ms_per_launch": round(kern["backproject"][0] / max(kern["backproject"][1], 1), 4)}
+                     "backproject_ms_per_launch": round(kern["backproject"][0] / max(kern["backproject"][1], 1), 4),
+                     "launches_per_step": kern["backproject"][1] // kern["reconstructions"],
+                     "graph_replay": {**stats(g_ms, updates), "equal_to_eager": bool(torch.equal(g_vol, vol))}}
         vols[name] = vol
         log(f"bench: C1 {name}: {out[name]}")
     pl = out["plain_f32"]
@@ -664,7 +701,7 @@ def leg_c4(b: Bench):
         r["compact_error_vs_oracle_rounded_data"] = error_stats(g, ref_r)
         # the same launch with FP32 (wide) staging: storage rounding alone
         b.at.apply(ctx, cand, wide_staging=True)
-        _, _, volw = b.run(ctx, proj, P, v, 1, 0, timing=False)
+        _, _, volw = b.run(ctx, proj, P, v, 1, 0, timing=None)
         gw = volw[lo:lo + bl, lo:lo + bl, lo:lo + bl].double().cpu().numpy()
         r["wide_error_vs_oracle_fp32_data"] = error_stats(gw, ref32)
         r["wide_error_vs_oracle_rounded_data"] = error_stats(gw, ref_r)

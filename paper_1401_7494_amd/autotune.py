@@ -35,10 +35,11 @@ class Candidate:
     tile_x: int = 64
     tap_split: int = -1        # fused path: views of every 8 read directly (-1 = tuned, 8 = all)
     direct_taps: bool = False  # fused path: no LDS stage at all
+    no_column: bool = False    # Part 1 per voxel even where u and w do not vary along z
 
     def key(self) -> str:
         return (f"{self.path}/{self.views_per_pass}/{self.z_unroll}/{self.tile_x}/"
-                f"{'direct' if self.direct_taps else self.tap_split}")
+                f"{'direct' if self.direct_taps else self.tap_split}" + ("/nocol" if self.no_column else ""))
 
 
 # The library's own choice for the call (BP_PATH_AUTO with every parameter tuned by the library).
@@ -158,7 +159,7 @@ def apply(ctx, cand: Candidate, **options) -> None:
     """Set the candidate's choices on a context; its options are reset to ``options`` plus the
     candidate's tap mode."""
     ctx.set_tuning(cand.path, cand.views_per_pass, cand.z_unroll, cand.tile_x)
-    ctx.set_options(direct_taps=cand.direct_taps, **options)
+    ctx.set_options(direct_taps=cand.direct_taps, no_column=cand.no_column, **options)
     ctx.set_tap_split(cand.tap_split)
 
 

@@ -129,29 +129,74 @@ struct CheckedSource {
         }
     }
 
-    // Taps (i0, j) and (i0+1, j) of row j, 0 off the detector.  Indices are
-    // clamped into the image before loading, so every load is in bounds.
-    // FP32 with PAIRS (W >= 2): one 8-byte load of the pixel pair at columns
-    // c, c + 1 with c = i0 clamped into [0, W - 2] -- both inside the row, so the
-    // load never reaches past the view's last pixel -- from which the two taps
-    // are picked (i0 = -1: (0, pixel 0); i0 = W - 1: (pixel W - 1, 0)).
-    __device__ __forceinline__ void taps_row(const View& v, int i0, int j, float& a, float& b) const
+    // The horizontal part of Part 3 at column position i0 + fx: a row's value is
+    // (1 - fx) P[i0] + fx P[i0 + 1], pixels off the detector 0.
+    //   single taps: the two pixels loaded one dword each at clamped, in-bounds
+    //     indices, zeroed by explicit row and column tests;
+    //   PAIRS (FP32, W >= 2): the pair at columns c, c + 1, c = i0 clamped into
+    //     [0, W - 2], as one 8-byte load, with per-column weights (w0, w1) of its two
+    //     pixels that put (1 - fx) and fx on the right ones and 0 on any other
+    //     (column -1 or W, or a pixel of the pair that is not a tap).  A row off the
+    //     detector is read at a byte offset outside [0, W H 4) -- negative rows as
+    //     offsets of 2^32 - k, rows below as offsets past the end, and a pair never
+    //     straddles either boundary -- which the buffer's range check returns as 0.
+    // Both give fmaf(fx, P[i0 + 1], (1 - fx) P[i0]) with the same roundings.
+    struct Col {
+        int i0;
+        float fx;
+        int c_bytes;  // pairs: byte offset of column c in a row
+        float w0, w1;
+    };
+
+    __device__ __forceinline__ Col col(int i0, float fx) const
     {
-        const bool rj = (j >= 0) & (j < H);
-        const int row = min(max(j, 0), H - 1) * W;
+        Col k;
+        k.i0 = i0;
+        k.fx = fx;
         if constexpr (PAIRS) {
             const int c = min(max(i0, 0), W - 2);
-            const f32x2_t q = raw_buffer_load_f32x2(v.pair_rs, (row + c) * (int)kElem, 0, 0);
-            const bool left = i0 < 0, right = i0 > W - 2;
-            a = (rj & !left) ? (right ? q.y : q.x) : 0.0f;
-            b = (rj & !right) ? (left ? q.x : q.y) : 0.0f;
+            const float g = 1.0f - fx;
+            k.c_bytes = c * (int)kElem;
+            k.w0 = c == i0 ? g : (c == i0 + 1 ? fx : 0.0f);
+            k.w1 = c + 1 == i0 ? g : (c + 1 == i0 + 1 ? fx : 0.0f);
         } else {
-            const bool c0 = i0 >= 0, c1 = i0 + 1 < W;
-            const float ta = tap(v, row + max(i0, 0));
-            const float tb = tap(v, row + min(i0 + 1, W - 1));
-            a = (rj & c0) ? ta : 0.0f;
-            b = (rj & c1) ? tb : 0.0f;
+            k.c_bytes = 0;
+            k.w0 = k.w1 = 0.0f;
         }
+        return k;
+    }
+
+    // Value of the bilinear interpolant at column k and row position j0 + fy (j0 in [-1, H]).
+    __device__ __forceinline__ float value(const View& v, const Col& k, int j0, float fy) const
+    {
+        float top, bot;
+        if constexpr (PAIRS) {
+            // both rows' offsets in the VGPR operand: the range check covers that operand only (an
+            // SGPR offset is added after it), so a row off the detector must be off in the VGPR
+            const int row_b = W * (int)kElem;
+            const int off = __mul24(j0, row_b) + k.c_bytes;
+            const f32x2_t q0 = raw_buffer_load_f32x2(v.pair_rs, off, 0, 0);
+            const f32x2_t q1 = raw_buffer_load_f32x2(v.pair_rs, off + row_b, 0, 0);
+            top = fmaf(k.w1, q0.y, k.w0 * q0.x);
+            bot = fmaf(k.w1, q1.y, k.w0 * q1.x);
+        } else {
+            // i0 in [-1, W] (a clamped column position reaches W)
+            const bool c0 = (k.i0 >= 0) & (k.i0 < W), c1 = k.i0 + 1 < W;
+            const int ia = min(max(k.i0, 0), W - 1), ib = min(k.i0 + 1, W - 1);
+            float p[2][2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int j = j0 + r;
+                const bool rj = (j >= 0) & (j < H);
+                const int row = min(max(j, 0), H - 1) * W;
+                const float ta = tap(v, row + ia), tb = tap(v, row + ib);
+                p[r][0] = (rj & c0) ? ta : 0.0f;
+                p[r][1] = (rj & c1) ? tb : 0.0f;
+            }
+            top = fmaf(k.fx, p[0][1], (1.0f - k.fx) * p[0][0]);
+            bot = fmaf(k.fx, p[1][1], (1.0f - k.fx) * p[1][0]);
+        }
+        return fmaf(fy, bot, (1.0f - fy) * top);
     }
 
     // Contribution of one view at (u, v, w); 0 unless w > 0 and the position
@@ -164,15 +209,30 @@ struct CheckedSource {
         s = ok ? s : 0.0f;
         t = ok ? t : 0.0f;
         const float fs = floorf(s), ft = floorf(t);
-        const int i0 = (int)fs, j0 = (int)ft;
-        const float fx = s - fs, fy = t - ft;
-        float a, b, c, d;
-        taps_row(vw, i0, j0, a, b);
-        taps_row(vw, i0, j0 + 1, c, d);
-        const float top = fmaf(fx, b - a, a);
-        const float bot = fmaf(fx, d - c, c);
-        const float val = fmaf(fy, bot - top, top);
+        const float val = value(vw, col((int)fs, s - fs), (int)ft, t - ft);
         return ok ? val * (r * r) : 0.0f;
+    }
+
+    // Column view (u and w do not depend on z, as for a circular orbit about z; w > 0 on the
+    // whole box): 1/w and the column are formed once for the thread's ZU voxels, per voxel only
+    // the row t(Z) = (v_xy + P[1][2] Z) / w.  Positions are clamped into [-1, W] x [-1, H]: a
+    // position at or beyond an edge weighs only pixels off the detector, as the zero-extended
+    // image gives (the interpolant is 0 there and continuous across the clamp).
+    template <int ZU>
+    __device__ __forceinline__ void column(const View& vw, float uxy, float vxy, float wxy, float p12,
+                                           const float (&Z)[ZU], float (&acc)[ZU]) const
+    {
+        const float r = __builtin_amdgcn_rcpf(wxy);
+        const float s = __builtin_amdgcn_fmed3f(uxy * r, -1.0f, (float)W);
+        const float fs = floorf(s);
+        const Col k = col((int)fs, s - fs);
+        const float r2 = r * r, dt = p12 * r, tb = vxy * r;
+#pragma unroll
+        for (int i = 0; i < ZU; ++i) {
+            const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), -1.0f, (float)H);
+            const float ft = floorf(t);
+            acc[i] = fmaf(value(vw, k, (int)ft, t - ft), r2, acc[i]);
+        }
     }
 };
 
@@ -452,6 +512,10 @@ template <>
 struct has_column<Patch16Source> {
     static constexpr bool value = true;
 };
+template <typename T, bool PAIRS>
+struct has_column<CheckedSource<T, PAIRS>> {
+    static constexpr bool value = true;
+};
 
 // One block = 256 threads covering a TX x (256/TX) tile of (x, y) columns and
 // ZU voxels along z; a wavefront covers TX x (64/TX) columns.  Narrow tiles
@@ -558,6 +622,12 @@ __global__ __launch_bounds__(kBlock) void backproject_kernel(
                                                   fmaf(c.p[6], Z[i], vxy), fmaf(c.p[10], Z[i], wxy));
             }
         } else {
+            if constexpr (has_column<Src>::value) {
+                if (c.mode == kModeColumn) {
+                    src.column(view, uxy, vxy, wxy, c.p[6], Z, acc);
+                    continue;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < ZU; ++i)
                 acc[i] += src.contrib(view, fmaf(c.p[2], Z[i], uxy), fmaf(c.p[6], Z[i], vxy),

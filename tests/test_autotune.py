@@ -91,7 +91,7 @@ def test_ensure_tuned_searches_once_then_reads_the_cache(tmp_path):
     assert best == cands[1] and info["source"] == "search"
     assert at.AUTO.key() in calls  # the library's own choice is always timed
     assert info["auto_ms"] == 5.0 and info["best_ms"] == 3.0
-    assert ctx.applied[-3:] == [("tuning", "fused", 64, 8, 16), ("options", (("direct_taps", False),)),
+    assert ctx.applied[-3:] == [("tuning", "fused", 64, 8, 16), ("options", (("direct_taps", False), ("no_column", False))),
                                 ("split", -1)]
     n = len(calls)
     best2, info2 = at.ensure_tuned(_FakeCtx(), vol, proj, None, 0.5, (0, 0, 0), cands=cands, cache_path=path,

@@ -936,20 +936,46 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     const int xs[2] = {bx * tx, min(bx * tx + tx - 1, box.nx - 1)};
     const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
     const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
+    // per axis and corner coordinate: the terms of u, v, w and their magnitudes (the constant
+    // column of P rides with z)
+    double tu[3][2], tv[3][2], tw[3][2], au[3][2], av[3][2], aw[3][2];
+    for (int e = 0; e < 2; ++e) {
+        const double X = (double)box.ox + (double)box.vs * xs[e];
+        const double Y = (double)box.oy + (double)box.vs * ys[e];
+        const double Z = (double)box.oz + (double)box.vs * zs[e];
+        tu[0][e] = (double)c.p[0] * X;
+        tv[0][e] = (double)c.p[4] * X;
+        tw[0][e] = (double)c.p[8] * X;
+        tu[1][e] = (double)c.p[1] * Y;
+        tv[1][e] = (double)c.p[5] * Y;
+        tw[1][e] = (double)c.p[9] * Y;
+        tu[2][e] = (double)c.p[2] * Z + (double)c.p[3];
+        tv[2][e] = (double)c.p[6] * Z + (double)c.p[7];
+        tw[2][e] = (double)c.p[10] * Z + (double)c.p[11];
+        au[0][e] = fabs(tu[0][e]);
+        av[0][e] = fabs(tv[0][e]);
+        aw[0][e] = fabs(tw[0][e]);
+        au[1][e] = fabs(tu[1][e]);
+        av[1][e] = fabs(tv[1][e]);
+        aw[1][e] = fabs(tw[1][e]);
+        au[2][e] = fabs((double)c.p[2] * Z) + fabs((double)c.p[3]);
+        av[2][e] = fabs((double)c.p[6] * Z) + fabs((double)c.p[7]);
+        aw[2][e] = fabs((double)c.p[10] * Z) + fabs((double)c.p[11]);
+    }
     bool left = true, right = true, top = true, bottom = true;
     double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0, err = 0.0;
+#pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const double X = (double)box.ox + (double)box.vs * xs[q & 1];
-        const double Y = (double)box.oy + (double)box.vs * ys[(q >> 1) & 1];
-        const double Z = (double)box.oz + (double)box.vs * zs[q >> 2];
-        const double u = (double)c.p[0] * X + (double)c.p[1] * Y + (double)c.p[2] * Z + (double)c.p[3];
-        const double v = (double)c.p[4] * X + (double)c.p[5] * Y + (double)c.p[6] * Z + (double)c.p[7];
-        const double w = (double)c.p[8] * X + (double)c.p[9] * Y + (double)c.p[10] * Z + (double)c.p[11];
+        const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+        const double u = tu[0][ex] + tu[1][ey] + tu[2][ez];
+        const double v = tv[0][ex] + tv[1][ey] + tv[2][ez];
+        const double w = tw[0][ex] + tw[1][ey] + tw[2][ez];
         left &= u <= -2.0 * w;
         right &= u >= (W + 1.0) * w;
         top &= v <= -2.0 * w;
         bottom &= v >= (H + 1.0) * w;
-        const double s = u / w + 1.0, t = v / w + 1.0;
+        const double rw = 1.0 / w;
+        const double s = fma(u, rw, 1.0), t = fma(v, rw, 1.0);
         smin = q ? fmin(smin, s) : s;
         smax = q ? fmax(smax, s) : s;
         tmin = q ? fmin(tmin, t) : t;
@@ -957,12 +983,10 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
         // first-order bound on the FP32 error of the pass's position (each FP32 operation rounds by
         // at most 2^-24 of its result; the reciprocal by 2^-23): 8 roundings on the magnitudes
         // of the terms of u (v) and of w, plus the +1 of the padded coordinate
-        const double au = fabs((double)c.p[0] * X) + fabs((double)c.p[1] * Y) + fabs((double)c.p[2] * Z) + fabs((double)c.p[3]);
-        const double av = fabs((double)c.p[4] * X) + fabs((double)c.p[5] * Y) + fabs((double)c.p[6] * Z) + fabs((double)c.p[7]);
-        const double aw = fabs((double)c.p[8] * X) + fabs((double)c.p[9] * Y) + fabs((double)c.p[10] * Z) + fabs((double)c.p[11]);
-        const double g = 8.0 * 0x1p-24;
-        const double es = g * (au + fabs(s - 1.0) * aw) / fabs(w) + 0x1p-23 * (2.0 * fabs(s) + 2.0);
-        const double et = g * (av + fabs(t - 1.0) * aw) / fabs(w) + 0x1p-23 * (2.0 * fabs(t) + 2.0);
+        const double g = 8.0 * 0x1p-24, arw = fabs(rw);
+        const double awq = aw[0][ex] + aw[1][ey] + aw[2][ez];
+        const double es = g * (au[0][ex] + au[1][ey] + au[2][ez] + fabs(s - 1.0) * awq) * arw + 0x1p-23 * (2.0 * fabs(s) + 2.0);
+        const double et = g * (av[0][ex] + av[1][ey] + av[2][ez] + fabs(t - 1.0) * awq) * arw + 0x1p-23 * (2.0 * fabs(t) + 2.0);
         err = fmax(err, fmax(es, et));
     }
     if (left | right | top | bottom) {
@@ -1101,31 +1125,38 @@ __device__ __forceinline__ float pixel_f32(const T* img, int W, int H, int i, in
     else return __builtin_bit_cast(float, (uint32_t)v << 16);
 }
 
-// Bilinear-patch staging copy: one thread per patch (r, c) of a (H+2) x (W+2) grid.
+// Bilinear-patch staging copy: a block covers 256 columns by kPatchRows rows of the (H+2) x (W+2)
+// grid of patches, a thread one column of them, top to bottom, so that it loads each pixel row once
+// (the lower corners of one patch are the upper corners of the next).
+constexpr int kPatchRows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void patch_kernel(const T* __restrict__ proj, int W, int H,
                                                     f32x4_t* __restrict__ out, ViewNeed need)
 {
     const int Wq = W + 2, Hq = H + 2;
     const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int r = (int)blockIdx.y;
     const int k = (int)blockIdx.z;
     if (need.vc && (k & 7) >= need.direct_eighths && need.vc[k].mode != kModeGuarded && need.big[k] == 0u)
         return;  // whole block: no tile reads this view's records
-    if (c >= Wq || r >= Hq) return;
+    if (c >= Wq) return;
+    const int r_begin = (int)blockIdx.y * kPatchRows, r_end = min(r_begin + kPatchRows, Hq);
     const T* img = proj + (size_t)k * W * H;
-    const int i = c - 1, j = r - 1;  // detector pixel of the patch's first corner
-    const float a = pixel_f32(img, W, H, i, j);
-    const float b = pixel_f32(img, W, H, i + 1, j);
-    const float cc = pixel_f32(img, W, H, i, j + 1);
-    const float d = pixel_f32(img, W, H, i + 1, j + 1);
-    const float dx = b - a;
-    f32x4_t q;
-    q.x = a;
-    q.y = dx;
-    q.z = cc - a;
-    q.w = (d - cc) - dx;
-    out[((size_t)k * Hq + r) * Wq + c] = q;
+    const int i = c - 1;  // detector column of the patches' first corners
+    f32x4_t* dst = out + ((size_t)k * Hq + r_begin) * Wq + c;
+    float a = pixel_f32(img, W, H, i, r_begin - 1), b = pixel_f32(img, W, H, i + 1, r_begin - 1);
+    for (int r = r_begin; r < r_end; ++r, dst += Wq) {
+        const float cc = pixel_f32(img, W, H, i, r), d = pixel_f32(img, W, H, i + 1, r);
+        const float dx = b - a;
+        f32x4_t q;
+        q.x = a;
+        q.y = dx;
+        q.z = cc - a;
+        q.w = (d - cc) - dx;
+        *dst = q;
+        a = cc;
+        b = d;
+    }
 }
 
 // Largest |pixel| of each view (as the bits of a non-negative float, which
@@ -1167,24 +1198,27 @@ __global__ __launch_bounds__(256) void patch16_kernel(const T* __restrict__ proj
 {
     const int Wq = W + 2, Hq = H + 2;
     const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int r = (int)blockIdx.y;
     const int k = (int)blockIdx.z;
     const float sc = patch16_scale(maxabs[k]);
-    if (c == 0 && r == 0) inv_scale[k] = 1.0f / sc;
-    if (c >= Wq || r >= Hq) return;
+    if (c == 0 && blockIdx.y == 0) inv_scale[k] = 1.0f / sc;
+    if (c >= Wq) return;
+    const int r_begin = (int)blockIdx.y * kPatchRows, r_end = min(r_begin + kPatchRows, Hq);
     const T* img = proj + (size_t)k * W * H;
-    const int i = c - 1, j = r - 1;
-    const float a = pixel_f32(img, W, H, i, j) * sc;
-    const float b = pixel_f32(img, W, H, i + 1, j) * sc;
-    const float cc = pixel_f32(img, W, H, i, j + 1) * sc;
-    const float d = pixel_f32(img, W, H, i + 1, j + 1) * sc;
-    const float dx = b - a;
-    f16x4_t q;
-    q.x = (_Float16)a;
-    q.y = (_Float16)dx;
-    q.z = (_Float16)(cc - a);
-    q.w = (_Float16)((d - cc) - dx);
-    out[((size_t)k * Hq + r) * Wq + c] = q;
+    const int i = c - 1;
+    f16x4_t* dst = out + ((size_t)k * Hq + r_begin) * Wq + c;
+    float a = pixel_f32(img, W, H, i, r_begin - 1) * sc, b = pixel_f32(img, W, H, i + 1, r_begin - 1) * sc;
+    for (int r = r_begin; r < r_end; ++r, dst += Wq) {
+        const float cc = pixel_f32(img, W, H, i, r) * sc, d = pixel_f32(img, W, H, i + 1, r) * sc;
+        const float dx = b - a;
+        f16x4_t q;
+        q.x = (_Float16)a;
+        q.y = (_Float16)dx;
+        q.z = (_Float16)(cc - a);
+        q.w = (_Float16)((d - cc) - dx);
+        *dst = q;
+        a = cc;
+        b = d;
+    }
 }
 
 template <class Src, bool PADDED, int TX>
@@ -1285,7 +1319,7 @@ hipError_t launch_patch(Dtype dt, const void* proj, int W, int H, int n, void* o
                         hipStream_t s)
 {
     const dim3 block(256, 1, 1);
-    const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)(H + 2), (unsigned)n);
+    const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)((H + 2 + kPatchRows - 1) / kPatchRows), (unsigned)n);
     f32x4_t* q = (f32x4_t*)out;
     switch (dt) {
     case Dtype::F32:
@@ -1350,7 +1384,7 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
     // a fill kernel rather than a memset node, so that the call can be captured in a graph
     hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, maxabs, n);
     const dim3 rgrid(64, (unsigned)n), block(256, 1, 1);
-    const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)(H + 2), (unsigned)n);
+    const dim3 grid((unsigned)((W + 2 + 255) / 256), (unsigned)((H + 2 + kPatchRows - 1) / kPatchRows), (unsigned)n);
     f16x4_t* q = (f16x4_t*)out;
     switch (dt) {
     case Dtype::F32:

@@ -271,8 +271,6 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     c.culled = (c.layout != bp::Layout::Checked || c.plan.path == BP_PATH_FUSED_DIRECT) && !c.lds &&
                !(ctx->options & BP_OPT_NO_CULL);
     c.tiles = bp::n_tiles(nx, ny, nz, c.plan.zu, c.plan.tx);
-    // share of the views of each 8 that read directly while the others are staged (tuned at L = 512)
-    c.split = ctx->tap_split >= 0 ? ctx->tap_split : (c.layout == bp::Layout::Patch ? 4 : 3);
     c.words = bp::cull_words(n_views);
     // Staging of the next pass overlaps the current pass when there are two or more passes.  Tuned:
     // compact records only (L = 512, 496 views: BF16 2068 -> 2151 GUPS); the FP32 staging kernel
@@ -281,6 +279,10 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     // FP32 input: the LDS stage holds the caller's pixels (a quarter of the bytes of the records)
     c.raw_stage = c.lds && c.layout == bp::Layout::Patch && ctx->cfg.proj_dtype == BP_F32 &&
                   !(ctx->options & BP_OPT_STAGE_RECORDS);
+    // share of the views of each 8 that read directly while the others are staged (tuned at L = 512,
+    // 496 views: FP32 pixel stages 1, 2342 GUPS against 2313 at 2 and 2297 with every view staged;
+    // FP32 record stages 4; compact records 3)
+    c.split = ctx->tap_split >= 0 ? ctx->tap_split : (c.raw_stage ? 1 : c.layout == bp::Layout::Patch ? 4 : 3);
     c.overlap = c.staged && n_views > c.plan.k && !(ctx->options & BP_OPT_SERIAL_STAGING) &&
                 (c.layout == bp::Layout::Patch16 || (ctx->options & BP_OPT_OVERLAP_STAGING));
     c.halves = c.overlap ? 2 : 1;

@@ -106,19 +106,22 @@ constexpr uint32_t kPoisonPattern = 0x7FC07FC0u;
 constexpr int kStageRecords = 2048;
 // Footprint table entries {x, y}: y == kFootprintSkip -> the tile misses the
 // detector in that view; y == kFootprintDirect -> read that view's taps
-// directly; otherwise x = cmin | rmin << 16, y = fw | fh << 16,
+// directly (patch records); y == kFootprintPixels (pixel stages only) -> the
+// footprint is too large for the stage, read the four pixels of each patch from
+// the caller's image; otherwise x = cmin | rmin << 16, y = fw | fh << 16,
 // with the kFootprintInner bit set in y when no position needs clamping into
 // the footprint (fw < 2^15).
-constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu;
+constexpr uint32_t kFootprintSkip = 0u, kFootprintDirect = 0xffffffffu, kFootprintPixels = 0xfffffffeu;
 constexpr uint32_t kFootprintInner = 0x8000u, kFootprintWidthMask = 0x7fffu;
 
 
 // Footprint table of one pass: n views (view constants vc[0, n)), every tile;
 // views with k % 8 < direct_eighths are marked to read their taps directly.
 // raw: footprints sized for staging FP32 pixels (fw < 64, fh < 36) rather
-// than patch records (fw <= 64, fh <= 32, fw fh <= kStageRecords).
-// big (may be null): big[k] = 1 for a view with a footprint too large for the
-// stage, whose records are then read directly (big zeroed beforehand).
+// than patch records (fw <= 64, fh <= 32, fw fh <= kStageRecords); a larger
+// footprint is then marked kFootprintPixels.
+// big (may be null; record stages): big[k] = 1 for a view with a footprint too
+// large for the stage, whose records are then read directly (big zeroed beforehand).
 hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_unroll, int tile_x, int W, int H,
                             bool raw, int direct_eighths, uint2* out, uint32_t* big, hipStream_t s);
 

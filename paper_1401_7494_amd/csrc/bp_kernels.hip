@@ -384,6 +384,30 @@ struct RawPatchSource : PatchSource {
         return rs;
     }
 
+    // The record of padded patch (r0, c0) (c0 in [0, W + 1], r0 in [0, H + 1]) from the view's
+    // pixels, zero off the detector, with the operations of patch_kernel.  Every tap is read at an
+    // index clamped into the image and zeroed by a select when it lies off the detector.  (The
+    // buffer's range check is not relied on here: the compiler merges the loads of two adjacent
+    // pixels into one 8-byte load, which is out of range as a whole when its first pixel is.)
+    __device__ __forceinline__ Rec raw_rec(const i32x4_t& rs, int c0, int r0) const
+    {
+        const int i = c0 - 1, j = r0 - 1;
+        const bool ca = (unsigned)i < (unsigned)W, cb = (unsigned)(i + 1) < (unsigned)W;
+        const bool ra = (unsigned)j < (unsigned)H, rb = (unsigned)(j + 1) < (unsigned)H;
+        const int ia = min(max(i, 0), W - 1), ib = min(i + 1, W - 1);
+        const int ja = min(max(j, 0), H - 1) * W, jb = min(j + 1, H - 1) * W;
+        const float a0 = raw_buffer_load_f32(rs, (ja + ia) * 4, 0, 0), b0 = raw_buffer_load_f32(rs, (ja + ib) * 4, 0, 0);
+        const float c1 = raw_buffer_load_f32(rs, (jb + ia) * 4, 0, 0), d1 = raw_buffer_load_f32(rs, (jb + ib) * 4, 0, 0);
+        const float a = (ra & ca) ? a0 : 0.0f, b = (ra & cb) ? b0 : 0.0f;
+        const float cc = (rb & ca) ? c1 : 0.0f, d = (rb & cb) ? d1 : 0.0f;
+        const float dx = b - a;
+        Rec q;
+        q.x = a;
+        q.y = dx;
+        q.z = cc - a;
+        q.w = (d - cc) - dx;
+        return q;
+    }
 };
 
 // Compact bilinear-patch layout for 16-bit projections: the same four
@@ -677,8 +701,15 @@ struct StageOf<Src, true> {
 // POISON (a testing aid, instantiated for ZU = 8 only): before each staged footprint is written,
 // every word of the LDS stage is set to a NaN pattern, so that any read of a stage element the
 // footprint did not write would turn the voxel's sum into NaN.
+// The pixel-stage pass is compiled for 8 waves per SIMD (at most 64 VGPRs): its LDS reads and
+// their arithmetic hide latency by occupancy (at L = 512: 32.4 -> 29.3 ms for a reconstruction
+// with every view staged, against 5 waves at 94 VGPRs).  Record stages keep the compiler's
+// choice: their directly read records need the registers to stay in flight.
+template <class Src>
+constexpr int kLdsWavesPerSimd = Src::kRawStage ? 8 : 1;
+
 template <class Src, int ZU, int TX, bool POISON = false>
-__global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
+__global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds_kernel(
     float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
     const uint2* __restrict__ fp, int xcd_order)
 {
@@ -750,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             }
         }
     };
-    auto staged = [](uint2 f) { return f.y != kFootprintSkip && f.y != kFootprintDirect; };
+    auto staged = [](uint2 f) { return f.y != kFootprintSkip && f.y != kFootprintDirect && f.y != kFootprintPixels; };
     auto stage = [&](StageT* buf, uint2 f) {  // the prefetched records or pixels into LDS
         const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
@@ -833,6 +864,41 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
             }
             continue;
         }
+        if constexpr (kRaw) {
+            if (f.y == kFootprintPixels) {
+                // a footprint too large for the stage: the patches' pixels from the caller's image,
+                // positions clamped into the bordered frame as the directly read views do
+                const i32x4_t rs = src.raw_view(k);
+                const float sw = (float)(src.W + 1), sh = (float)(src.H + 1);
+                if (c.mode == kModeColumn) {
+                    const float r = __builtin_amdgcn_rcpf(wxy);
+                    const float sc = __builtin_amdgcn_fmed3f(fmaf(uxy, r, 1.0f), 0.0f, sw);
+                    const int c0 = (int)sc;
+                    const float fx = __builtin_amdgcn_fractf(sc);
+                    const float r2 = src.weight_column(view, r);
+                    const float dt = c.p[6] * r;
+                    const float tb = fmaf(vxy, r, 1.0f);
+#pragma unroll
+                    for (int i = 0; i < ZU; ++i) {
+                        const float t = __builtin_amdgcn_fmed3f(fmaf(Z[i], dt, tb), 0.0f, sh);
+                        const Rec q = src.raw_rec(rs, c0, (int)t);
+                        acc[i] = fmaf(Src::eval(q, fx, __builtin_amdgcn_fractf(t)), r2, acc[i]);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < ZU; ++i) {
+                        const float w = fmaf(c.p[10], Z[i], wxy);
+                        const float r = __builtin_amdgcn_rcpf(w);
+                        const float sv = __builtin_amdgcn_fmed3f(fmaf(fmaf(c.p[2], Z[i], uxy), r, 1.0f), 0.0f, sw);
+                        const float tv = __builtin_amdgcn_fmed3f(fmaf(fmaf(c.p[6], Z[i], vxy), r, 1.0f), 0.0f, sh);
+                        const Rec q = src.raw_rec(rs, (int)sv, (int)tv);
+                        acc[i] += Src::eval(q, __builtin_amdgcn_fractf(sv), __builtin_amdgcn_fractf(tv)) *
+                                  src.weight_voxel(view, r);
+                    }
+                }
+                continue;
+            }
+        }
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         // byte offsets of the stage, so that a row's address is one 24-bit multiply-add:
@@ -913,16 +979,17 @@ __global__ __launch_bounds__(kBlock) void backproject_lds_kernel(
 // than the FP32 rounding of the pass, and is cut to the bordered frame
 // [0, W+1] x [0, H+1].  Entry {0, kFootprintSkip}: the tile projects off the
 // detector (the test of cull_kernel, exact zeros); {0, kFootprintDirect}: a
-// guarded view, a footprint wider than max_w records, taller than max_h or
-// of more than `cap` records, or one of the views k with
+// guarded view, a footprint (of a record stage) wider than max_w records,
+// taller than max_h or of more than `cap` records, or one of the views k with
 // k % 8 < direct_eighths -- those read their taps directly, so that the
-// pass draws on the L1 path and the LDS path at once.  The kFootprintInner
+// pass draws on the L1 path and the LDS path at once; {0, kFootprintPixels}:
+// a pixel stage's footprint beyond those bounds (its pixels are read directly).  The kFootprintInner
 // bit of a staged entry's width field marks an interior footprint, whose
 // positions need no clamp.  One thread per (tile, view).
 // ---------------------------------------------------------------------------
 __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
                                  int gx, int gy, int n_tiles, int W, int H, int cap, int max_w, int max_h,
-                                 int direct_eighths, uint2* __restrict__ out, uint32_t* __restrict__ big)
+                                 int direct_eighths, bool raw, uint2* __restrict__ out, uint32_t* __restrict__ big)
 {
     const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (long)n_tiles * n_views) return;
@@ -1009,6 +1076,10 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     const int r1 = (int)fmin(fmax(floor(tmax) + 1.0, 0.0), (double)(H + 1));
     const int fw = max(c1 - c0 + 1, 1), fh = max(r1 - r0 + 1, 1);
     if (fw > max_w || fh > max_h || (long)fw * fh > cap) {
+        if (raw) {  // the tile reads the caller's pixels: no records for this view
+            out[id] = make_uint2(0u, kFootprintPixels);
+            return;
+        }
         out[id] = make_uint2(0u, kFootprintDirect);
         if (big) big[k] = 1u;  // this view's records are read after all (every writer stores 1)
         return;
@@ -1374,7 +1445,7 @@ hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_un
     hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
                        n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, raw ? kRawStride * kRawRows : kStageRecords,
                        raw ? kStageMaxWidth - 1 : kStageMaxWidth, raw ? kRawRows - 1 : kStageMaxHeight,
-                       direct_eighths, out, big);
+                       direct_eighths, raw, out, big);
     return hipGetLastError();
 }
 

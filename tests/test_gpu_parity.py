@@ -533,7 +533,8 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
     """Taps staged through LDS per (tile, view) footprint give the same bits as direct taps, for any
     share of views read directly and with FP32 footprints staged as pixels or as records: column and
     general branches, culled tiles, guarded views (direct inside the staged pass), footprints too
-    large for LDS (direct as well), and footprints at the detector's edges (zero pixels)."""
+    large for LDS (records read directly, or with a pixel stage the caller's pixels, zero-extended at
+    the detector's edges), and footprints at the detector's edges (zero pixels)."""
     sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)
     proj = synth.filtered_projections(sc, synth.random_ellipsoids(77))
     if dtype != "f32":

@@ -983,92 +983,24 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
 // taller than max_h or of more than `cap` records, or one of the views k with
 // k % 8 < direct_eighths -- those read their taps directly, so that the
 // pass draws on the L1 path and the LDS path at once; {0, kFootprintPixels}:
-// a pixel stage's footprint beyond those bounds (its pixels are read directly).  The kFootprintInner
-// bit of a staged entry's width field marks an interior footprint, whose
-// positions need no clamp.  One thread per (tile, view).
+// a pixel stage's footprint beyond those bounds (its pixels are read directly).
+// The kFootprintInner bit of a staged entry's width field marks an interior
+// footprint, whose positions need no clamp.
 // ---------------------------------------------------------------------------
-__global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
-                                 int gx, int gy, int n_tiles, int W, int H, int cap, int max_w, int max_h,
-                                 int direct_eighths, bool raw, uint2* __restrict__ out, uint32_t* __restrict__ big)
+// The footprint table entry of one (tile, view) from the range of its corners' padded positions and
+// the bound on the FP32 error of the pass's positions.
+__device__ uint2 footprint_entry(bool skip, double smin, double smax, double tmin, double tmax, double err, int k,
+                                 int W, int H, int cap, int max_w, int max_h, int direct_eighths, bool raw,
+                                 uint32_t* __restrict__ big)
 {
-    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (long)n_tiles * n_views) return;
-    const int tile = (int)(id / n_views), k = (int)(id % n_views);
-    const ViewConst& c = vc[k];
-    if (c.mode == kModeGuarded) {
-        out[id] = make_uint2(0u, kFootprintDirect);
-        return;
-    }
-    const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
-    const int xs[2] = {bx * tx, min(bx * tx + tx - 1, box.nx - 1)};
-    const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
-    const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
-    // per axis and corner coordinate: the terms of u, v, w and their magnitudes (the constant
-    // column of P rides with z)
-    double tu[3][2], tv[3][2], tw[3][2], au[3][2], av[3][2], aw[3][2];
-    for (int e = 0; e < 2; ++e) {
-        const double X = (double)box.ox + (double)box.vs * xs[e];
-        const double Y = (double)box.oy + (double)box.vs * ys[e];
-        const double Z = (double)box.oz + (double)box.vs * zs[e];
-        tu[0][e] = (double)c.p[0] * X;
-        tv[0][e] = (double)c.p[4] * X;
-        tw[0][e] = (double)c.p[8] * X;
-        tu[1][e] = (double)c.p[1] * Y;
-        tv[1][e] = (double)c.p[5] * Y;
-        tw[1][e] = (double)c.p[9] * Y;
-        tu[2][e] = (double)c.p[2] * Z + (double)c.p[3];
-        tv[2][e] = (double)c.p[6] * Z + (double)c.p[7];
-        tw[2][e] = (double)c.p[10] * Z + (double)c.p[11];
-        au[0][e] = fabs(tu[0][e]);
-        av[0][e] = fabs(tv[0][e]);
-        aw[0][e] = fabs(tw[0][e]);
-        au[1][e] = fabs(tu[1][e]);
-        av[1][e] = fabs(tv[1][e]);
-        aw[1][e] = fabs(tw[1][e]);
-        au[2][e] = fabs((double)c.p[2] * Z) + fabs((double)c.p[3]);
-        av[2][e] = fabs((double)c.p[6] * Z) + fabs((double)c.p[7]);
-        aw[2][e] = fabs((double)c.p[10] * Z) + fabs((double)c.p[11]);
-    }
-    bool left = true, right = true, top = true, bottom = true;
-    double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0, err = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
-        const double u = tu[0][ex] + tu[1][ey] + tu[2][ez];
-        const double v = tv[0][ex] + tv[1][ey] + tv[2][ez];
-        const double w = tw[0][ex] + tw[1][ey] + tw[2][ez];
-        left &= u <= -2.0 * w;
-        right &= u >= (W + 1.0) * w;
-        top &= v <= -2.0 * w;
-        bottom &= v >= (H + 1.0) * w;
-        const double rw = 1.0 / w;
-        const double s = fma(u, rw, 1.0), t = fma(v, rw, 1.0);
-        smin = q ? fmin(smin, s) : s;
-        smax = q ? fmax(smax, s) : s;
-        tmin = q ? fmin(tmin, t) : t;
-        tmax = q ? fmax(tmax, t) : t;
-        // first-order bound on the FP32 error of the pass's position (each FP32 operation rounds by
-        // at most 2^-24 of its result; the reciprocal by 2^-23): 8 roundings on the magnitudes
-        // of the terms of u (v) and of w, plus the +1 of the padded coordinate
-        const double g = 8.0 * 0x1p-24, arw = fabs(rw);
-        const double awq = aw[0][ex] + aw[1][ey] + aw[2][ez];
-        const double es = g * (au[0][ex] + au[1][ey] + au[2][ez] + fabs(s - 1.0) * awq) * arw + 0x1p-23 * (2.0 * fabs(s) + 2.0);
-        const double et = g * (av[0][ex] + av[1][ey] + av[2][ez] + fabs(t - 1.0) * awq) * arw + 0x1p-23 * (2.0 * fabs(t) + 2.0);
-        err = fmax(err, fmax(es, et));
-    }
-    if (left | right | top | bottom) {
-        out[id] = make_uint2(0u, kFootprintSkip);
-        return;
-    }
+    if (skip) return make_uint2(0u, kFootprintSkip);
     // Interior: the rectangle below (one record of margin on each side of the corners' range) lies
     // inside the bordered frame without cutting, and the FP32 position error of the pass is far
     // below that margin, so no position of the tile needs clamping.  (NaN compares false.)
     const bool inner = err < 0.25 && floor(smin) - 1.0 >= 0.0 && floor(smax) + 1.0 <= (double)(W + 1) &&
                        floor(tmin) - 1.0 >= 0.0 && floor(tmax) + 1.0 <= (double)(H + 1);
-    if ((k & 7) < direct_eighths) {  // this share of the views reads its taps directly (through L1)
-        out[id] = make_uint2(0u, kFootprintDirect);
-        return;
-    }
+    // this share of the views reads its taps directly (through L1)
+    if ((k & 7) < direct_eighths) return make_uint2(0u, kFootprintDirect);
     // fmin / fmax also map a NaN to the frame
     const int c0 = (int)fmin(fmax(floor(smin) - 1.0, 0.0), (double)(W + 1));
     const int c1 = (int)fmin(fmax(floor(smax) + 1.0, 0.0), (double)(W + 1));
@@ -1076,16 +1008,140 @@ __global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, 
     const int r1 = (int)fmin(fmax(floor(tmax) + 1.0, 0.0), (double)(H + 1));
     const int fw = max(c1 - c0 + 1, 1), fh = max(r1 - r0 + 1, 1);
     if (fw > max_w || fh > max_h || (long)fw * fh > cap) {
-        if (raw) {  // the tile reads the caller's pixels: no records for this view
-            out[id] = make_uint2(0u, kFootprintPixels);
-            return;
-        }
-        out[id] = make_uint2(0u, kFootprintDirect);
+        if (raw) return make_uint2(0u, kFootprintPixels);  // the tile reads the caller's pixels
         if (big) big[k] = 1u;  // this view's records are read after all (every writer stores 1)
+        return make_uint2(0u, kFootprintDirect);
+    }
+    return make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16),
+                      (uint32_t)fw | (inner ? kFootprintInner : 0u) | ((uint32_t)fh << 16));
+}
+
+// First-order bound on the FP32 error of a padded position p = n / w + 1 as the pass forms it (each
+// FP32 operation rounds by at most 2^-24 of its result, the reciprocal by 2^-23): 8 roundings on the
+// magnitudes an (of the terms of the numerator) and aw (of w), plus the +1.
+__device__ __forceinline__ double position_error(double p, double an, double aw, double arw)
+{
+    return 8.0 * 0x1p-24 * (an + fabs(p - 1.0) * aw) * arw + 0x1p-23 * (2.0 * fabs(p) + 2.0);
+}
+
+// One thread per (column of tiles (bx, by), view): the entries of every z-layer of tiles.  For a
+// column view (u and w do not depend on z) the reciprocals of w and the column positions are formed
+// once, at the 4 (x, y) corners, and each z-layer only adds its rows; other views take all 8 corners
+// of each tile.
+__global__ void footprint_kernel(const ViewConst* __restrict__ vc, int n_views, Box box, int tx, int ty, int tz,
+                                 int gx, int gy, int gz, int W, int H, int cap, int max_w, int max_h,
+                                 int direct_eighths, bool raw, uint2* __restrict__ out, uint32_t* __restrict__ big)
+{
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)gx * gy * n_views) return;
+    const int xy = (int)(id / n_views), k = (int)(id % n_views);
+    const long layer = (long)gx * gy * n_views;  // entries of one z-layer of tiles
+    uint2* o = out + id;                           // tile (bx, by, bz), view k: o[bz * layer]
+    const ViewConst& c = vc[k];
+    if (c.mode == kModeGuarded) {
+        for (int bz = 0; bz < gz; ++bz) o[bz * layer] = make_uint2(0u, kFootprintDirect);
         return;
     }
-    out[id] = make_uint2((uint32_t)c0 | ((uint32_t)r0 << 16),
-                         (uint32_t)fw | (inner ? kFootprintInner : 0u) | ((uint32_t)fh << 16));
+    const int bx = xy % gx, by = xy / gx;
+    const int xs[2] = {bx * tx, min(bx * tx + tx - 1, box.nx - 1)};
+    const int ys[2] = {by * ty, min(by * ty + ty - 1, box.ny - 1)};
+    // per axis and corner coordinate: the terms of u, v, w and their magnitudes
+    double tu[2][2], tv[2][2], tw[2][2], au[2][2], av[2][2], aw[2][2];
+    for (int e = 0; e < 2; ++e) {
+        const double X = (double)box.ox + (double)box.vs * xs[e];
+        const double Y = (double)box.oy + (double)box.vs * ys[e];
+        tu[0][e] = (double)c.p[0] * X;
+        tv[0][e] = (double)c.p[4] * X;
+        tw[0][e] = (double)c.p[8] * X;
+        tu[1][e] = (double)c.p[1] * Y;
+        tv[1][e] = (double)c.p[5] * Y;
+        tw[1][e] = (double)c.p[9] * Y;
+        for (int a = 0; a < 2; ++a) {
+            au[a][e] = fabs(tu[a][e]);
+            av[a][e] = fabs(tv[a][e]);
+            aw[a][e] = fabs(tw[a][e]);
+        }
+    }
+    if (c.mode == kModeColumn) {
+        // P[0][2] = P[2][2] = 0: u, w and the column positions at the 4 (x, y) corners
+        double rw[4], vxy[4], avxy[4], wq[4], awq[4];
+        bool left = true, right = true;
+        double smin = 0.0, smax = 0.0, es = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ex = q & 1, ey = q >> 1;
+            const double u = tu[0][ex] + tu[1][ey] + (double)c.p[3];
+            const double w = tw[0][ex] + tw[1][ey] + (double)c.p[11];
+            left &= u <= -2.0 * w;
+            right &= u >= (W + 1.0) * w;
+            rw[q] = 1.0 / w;
+            wq[q] = w;
+            vxy[q] = tv[0][ex] + tv[1][ey];
+            avxy[q] = av[0][ex] + av[1][ey] + fabs((double)c.p[7]);
+            awq[q] = aw[0][ex] + aw[1][ey] + fabs((double)c.p[11]);
+            const double sq = fma(u, rw[q], 1.0);
+            smin = q ? fmin(smin, sq) : sq;
+            smax = q ? fmax(smax, sq) : sq;
+            es = fmax(es, position_error(sq, au[0][ex] + au[1][ey] + fabs((double)c.p[3]), awq[q], fabs(rw[q])));
+        }
+        for (int bz = 0; bz < gz; ++bz) {
+            const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
+            bool top = true, bottom = true;
+            double tmin = 0.0, tmax = 0.0, err = es;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ez = q >> 2, cq = q & 3;
+                const double pz = (double)c.p[6] * ((double)box.oz + (double)box.vs * zs[ez]);
+                const double v = vxy[cq] + pz + (double)c.p[7];
+                top &= v <= -2.0 * wq[cq];
+                bottom &= v >= (H + 1.0) * wq[cq];
+                const double t = fma(v, rw[cq], 1.0);
+                tmin = q ? fmin(tmin, t) : t;
+                tmax = q ? fmax(tmax, t) : t;
+                err = fmax(err, position_error(t, avxy[cq] + fabs(pz), awq[cq], fabs(rw[cq])));
+            }
+            o[bz * layer] = footprint_entry(left | right | top | bottom, smin, smax, tmin, tmax, err, k, W, H, cap,
+                                            max_w, max_h, direct_eighths, raw, big);
+        }
+        return;
+    }
+    for (int bz = 0; bz < gz; ++bz) {
+        const int zs[2] = {bz * tz, min(bz * tz + tz - 1, box.nz - 1)};
+        double tu2[2], tv2[2], tw2[2], au2[2], av2[2], aw2[2];  // z terms with the constant column
+        for (int e = 0; e < 2; ++e) {
+            const double Z = (double)box.oz + (double)box.vs * zs[e];
+            tu2[e] = (double)c.p[2] * Z + (double)c.p[3];
+            tv2[e] = (double)c.p[6] * Z + (double)c.p[7];
+            tw2[e] = (double)c.p[10] * Z + (double)c.p[11];
+            au2[e] = fabs((double)c.p[2] * Z) + fabs((double)c.p[3]);
+            av2[e] = fabs((double)c.p[6] * Z) + fabs((double)c.p[7]);
+            aw2[e] = fabs((double)c.p[10] * Z) + fabs((double)c.p[11]);
+        }
+        bool left = true, right = true, top = true, bottom = true;
+        double smin = 0.0, smax = 0.0, tmin = 0.0, tmax = 0.0, err = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ex = q & 1, ey = (q >> 1) & 1, ez = q >> 2;
+            const double u = tu[0][ex] + tu[1][ey] + tu2[ez];
+            const double v = tv[0][ex] + tv[1][ey] + tv2[ez];
+            const double w = tw[0][ex] + tw[1][ey] + tw2[ez];
+            left &= u <= -2.0 * w;
+            right &= u >= (W + 1.0) * w;
+            top &= v <= -2.0 * w;
+            bottom &= v >= (H + 1.0) * w;
+            const double rw = 1.0 / w;
+            const double s = fma(u, rw, 1.0), t = fma(v, rw, 1.0);
+            smin = q ? fmin(smin, s) : s;
+            smax = q ? fmax(smax, s) : s;
+            tmin = q ? fmin(tmin, t) : t;
+            tmax = q ? fmax(tmax, t) : t;
+            const double awq = aw[0][ex] + aw[1][ey] + aw2[ez], arw = fabs(rw);
+            err = fmax(err, fmax(position_error(s, au[0][ex] + au[1][ey] + au2[ez], awq, arw),
+                                 position_error(t, av[0][ex] + av[1][ey] + av2[ez], awq, arw)));
+        }
+        o[bz * layer] = footprint_entry(left | right | top | bottom, smin, smax, tmin, tmax, err, k, W, H, cap, max_w,
+                                        max_h, direct_eighths, raw, big);
+    }
 }
 
 __global__ void zero_u32_kernel(uint32_t* __restrict__ p, int n)
@@ -1439,11 +1495,11 @@ hipError_t launch_footprint(const ViewConst* vc, int n, const Box& box, int z_un
 {
     const int tx = tile_x, ty = kBlock / tile_x;
     const int gx = (box.nx + tx - 1) / tx, gy = (box.ny + ty - 1) / ty;
-    const long tiles = n_tiles(box.nx, box.ny, box.nz, z_unroll, tile_x);
-    const long total = tiles * n;
+    const int gz = (box.nz + z_unroll - 1) / z_unroll;
+    const long total = (long)gx * gy * n;
     const int threads = 256;
     hipLaunchKernelGGL(footprint_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s, vc,
-                       n, box, tx, ty, z_unroll, gx, gy, (int)tiles, W, H, raw ? kRawStride * kRawRows : kStageRecords,
+                       n, box, tx, ty, z_unroll, gx, gy, gz, W, H, raw ? kRawStride * kRawRows : kStageRecords,
                        raw ? kStageMaxWidth - 1 : kStageMaxWidth, raw ? kRawRows - 1 : kStageMaxHeight,
                        direct_eighths, raw, out, big);
     return hipGetLastError();

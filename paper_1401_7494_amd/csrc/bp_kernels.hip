@@ -239,10 +239,13 @@ struct CheckedSource {
 // Fused path, bilinear-patch layout: element (r, c) of a (H + 2) x (W + 2) grid
 // holds the four coefficients of the bilinear patch whose corners are the
 // zero-padded pixels (r, c), (r, c+1), (r+1, c), (r+1, c+1) -- padded pixel
-// (r, c) is detector pixel (c - 1, r - 1):
-//     a = P(r,c), dx = P(r,c+1) - a, dy = P(r+1,c) - a, dxy = P(r+1,c+1) - P(r+1,c) - dx
-// so B = a + fx dx + fy (dy + fx dxy): one 16-byte load and three FMAs per
-// voxel update instead of four taps and three lerps.  The coefficients are
+// (r, c) is detector pixel (c - 1, r - 1): the left pixel of each of the two
+// rows and its difference to the right one,
+//     a = P(r,c), dx = P(r,c+1) - a, c = P(r+1,c), dx' = P(r+1,c+1) - c,
+// so the two rows' lerps along x are one FMA each, top = a + fx dx and
+// bot = c + fx dx', and B = top + fy (bot - top): one 16-byte load instead of
+// four taps, and the same two subtractions and three FMAs whether an update
+// forms the coefficients from four pixels or reads them.  The coefficients are
 // FP32 whatever the storage type of the projections.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -291,10 +294,11 @@ struct PatchSource {
         return struct_buffer_load_f32x4(vw.rs, idx, 0, 0, 0);
     }
 
-    // Part 3 on one patch: a + fx dx + fy (dy + fx dxy).
+    // Part 3 on one patch: the lerps of the two rows along x, then the lerp between them along y.
     static __device__ __forceinline__ float eval(const Rec& q, float fx, float fy)
     {
-        return fmaf(fx, q.y, fmaf(fy, fmaf(fx, q.w, q.z), q.x));
+        const float top = fmaf(fx, q.y, q.x), bot = fmaf(fx, q.w, q.z);
+        return fmaf(fy, bot - top, top);
     }
 
     // 1/w^2 from r = 1/w: as the column branch and the per-voxel branch form it.
@@ -400,18 +404,18 @@ struct RawPatchSource : PatchSource {
         const float c1 = raw_buffer_load_f32(rs, (jb + ia) * 4, 0, 0), d1 = raw_buffer_load_f32(rs, (jb + ib) * 4, 0, 0);
         const float a = (ra & ca) ? a0 : 0.0f, b = (ra & cb) ? b0 : 0.0f;
         const float cc = (rb & ca) ? c1 : 0.0f, d = (rb & cb) ? d1 : 0.0f;
-        const float dx = b - a;
         Rec q;
         q.x = a;
-        q.y = dx;
-        q.z = cc - a;
-        q.w = (d - cc) - dx;
+        q.y = b - a;
+        q.z = cc;
+        q.w = d - cc;
         return q;
     }
 };
 
-// Compact bilinear-patch layout for 16-bit projections: the same four
-// coefficients as PatchSource, stored as FP16 (8 bytes per record) after
+// Compact bilinear-patch layout for 16-bit projections: the four coefficients
+//     a = P(r,c), dx = P(r,c+1) - a, dy = P(r+1,c) - a, dxy = P(r+1,c+1) - P(r+1,c) - dx
+// of the patch, B = a + fx dx + fy (dy + fx dxy), stored as FP16 (8 bytes per record) after
 // scaling view k by a power of two, 2^e_k, chosen from the view's largest
 // |pixel| so that no coefficient can overflow FP16 (|dxy| <= 4 max|p| <=
 // 2^13).  v_fma_mix_f32 evaluates FP16 coefficients with FP32 weights and
@@ -805,15 +809,14 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
     auto staged_rec = [&](uint32_t off) -> Rec {
         const char* lds_b = reinterpret_cast<const char*>(lds);
         if constexpr (kRaw) {
-            // the record (a, dx, dy, dxy) of the four pixels with the roundings of patch_kernel
+            // the record (a, b - a, c, d - c) of the four pixels with the roundings of patch_kernel
             const float* q = static_cast<const float*>(__builtin_assume_aligned(lds_b + off, 4));
             const float a = q[0], b = q[1], cc = q[kRawStride], d = q[kRawStride + 1];
-            const float dx = b - a;
             Rec r;
             r.x = a;
-            r.y = dx;
-            r.z = cc - a;
-            r.w = (d - cc) - dx;
+            r.y = b - a;
+            r.z = cc;
+            r.w = d - cc;
             return r;
         } else {
             return *static_cast<const Rec*>(__builtin_assume_aligned(lds_b + off, sizeof(Rec)));
@@ -1274,12 +1277,11 @@ __global__ __launch_bounds__(256) void patch_kernel(const T* __restrict__ proj, 
     float a = pixel_f32(img, W, H, i, r_begin - 1), b = pixel_f32(img, W, H, i + 1, r_begin - 1);
     for (int r = r_begin; r < r_end; ++r, dst += Wq) {
         const float cc = pixel_f32(img, W, H, i, r), d = pixel_f32(img, W, H, i + 1, r);
-        const float dx = b - a;
         f32x4_t q;
         q.x = a;
-        q.y = dx;
-        q.z = cc - a;
-        q.w = (d - cc) - dx;
+        q.y = b - a;
+        q.z = cc;
+        q.w = d - cc;
         *dst = q;
         a = cc;
         b = d;

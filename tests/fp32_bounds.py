@@ -135,8 +135,7 @@ def emulate_fp32(proj, P32, shape, vs, origin, swap_taps=False):
         if swap_taps:
             b, c = c, b
         dx = _f32(b - a)
-        dy = _f32(c - a)
-        dxy = _f32(_f32(d - c) - dx)
+        dx2 = _f32(d - c)
         p = P[k]
         uu = _fma(p[0, 2], Z, _fma(p[0, 1], Y, _fma(p[0, 0], X, p[0, 3])))
         vv = _fma(p[1, 2], Z, _fma(p[1, 1], Y, _fma(p[1, 0], X, p[1, 3])))
@@ -152,7 +151,9 @@ def emulate_fp32(proj, P32, shape, vs, origin, swap_taps=False):
         r0 = np.floor(t).astype(np.int64)
         fx = _f32(s - c0)
         fy = _f32(t - r0)
-        val = _fma(fx, dx[r0, c0], _fma(fy, _fma(fx, dxy[r0, c0], dy[r0, c0]), a[r0, c0]))
+        top = _fma(fx, dx[r0, c0], a[r0, c0])
+        bot = _fma(fx, dx2[r0, c0], c[r0, c0])
+        val = _fma(fy, _f32(bot - top), top)
         with np.errstate(invalid="ignore", over="ignore"):
             contrib = np.where(ok, _f32(val * _f32(r * r)), 0.0)
         acc = _f32(acc + contrib)

@@ -268,8 +268,8 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
         c.layout = bp::Layout::Patch16;
     // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
     c.lds = !c.plan.direct_taps && staged_taps(ctx, c.layout, W, H);
-    c.culled = (c.layout != bp::Layout::Checked || c.plan.path == BP_PATH_FUSED_DIRECT) && !c.lds &&
-               !(ctx->options & BP_OPT_NO_CULL);
+    // clipping mask for every pass that does not stage footprints (which carry their own skip entries)
+    c.culled = !c.lds && !(ctx->options & BP_OPT_NO_CULL);
     c.tiles = bp::n_tiles(nx, ny, nz, c.plan.zu, c.plan.tx);
     c.words = bp::cull_words(n_views);
     // Staging of the next pass overlaps the current pass when there are two or more passes.  Tuned:
@@ -683,8 +683,7 @@ bp_status bp_backproject_noalloc(bp_ctx ctx, float* volume, int nx, int ny, int 
     const size_t mask_off = (views_bytes + 255) & ~size_t(255);
     const int words = bp::cull_words(n_views);
     const size_t mask_bytes = (size_t)bp::n_tiles(nx, ny, nz, plan.zu, plan.tx) * (size_t)words * 4u;
-    const bool culled = plan.path == BP_PATH_FUSED_DIRECT && !(ctx->options & BP_OPT_NO_CULL) &&
-                        mask_off + mask_bytes <= bp::kNoAllocScratchBytes;
+    const bool culled = !(ctx->options & BP_OPT_NO_CULL) && mask_off + mask_bytes <= bp::kNoAllocScratchBytes;
     bp::ViewConst* vc = static_cast<bp::ViewConst*>(ctx->noalloc);
     uint32_t* mask = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(ctx->noalloc) + mask_off);
     const bool column_ok = !(ctx->options & BP_OPT_NO_COLUMN);

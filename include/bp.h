@@ -163,16 +163,20 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 
 /*
  * Options (bit flags, default 0; results are equal whatever the flags, up to
- * FP32 rounding for BP_OPT_NO_COLUMN and FP16 rounding for BP_OPT_WIDE_STAGING):
+ * FP32 rounding for BP_OPT_NO_COLUMN and FP16 rounding for BP_OPT_COMPACT_STAGING):
  *   BP_OPT_NO_CULL    do not skip (tile, view) pairs whose whole tile projects
  *                     off the detector (the clipping mask of Sec. 5)
  *   BP_OPT_NO_COLUMN  do not specialise views whose matrix has P[0][2] = P[2][2] = 0
  *                     (u and w constant along z, as for a circular orbit about z)
- *   BP_OPT_WIDE_STAGING  stage FP16/BF16 projections as FP32 bilinear-patch
- *                     coefficients (16 bytes per pixel) instead of the default
- *                     compact FP16 coefficients (8 bytes, scaled per view by a
- *                     power of two; adds the rounding of the pixel differences
- *                     to FP16, ~2^-11 relative)
+ *   BP_OPT_COMPACT_STAGING  FP16/BF16 projections: stage them as compact FP16
+ *                     bilinear-patch coefficients (8 bytes per pixel, scaled per
+ *                     view by a power of two; adds the rounding of the pixel
+ *                     differences to FP16, ~2^-11 relative) instead of the
+ *                     default, which treats them as FP32 projections: their
+ *                     pixels (exactly widened) staged in LDS and FP32
+ *                     coefficients for the views read directly
+ *   BP_OPT_WIDE_STAGING  FP16/BF16 projections: the default FP32 staging, named
+ *                     (with BP_OPT_COMPACT_STAGING: an error)
  *   BP_OPT_DIRECT_TAPS  fused path: read every tap directly through the vector
  *                     L1 cache.  By default the fused path copies, for every
  *                     (block tile, view), the tile's footprint of the staging
@@ -191,10 +195,11 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     serial for FP32 records (whose staging contends with the
  *                     pass for the vector memory path).  Both flags: an error.
  *                     Results are bit-identical in every case.
- *   BP_OPT_STAGE_RECORDS  fused path, FP32 projections: copy the LDS footprints
- *                     as 16-byte patch records rather than as the caller's FP32
- *                     pixels (from which each update then forms its patch with
- *                     the staging copy's own FP32 operations).  Bit-identical.
+ *   BP_OPT_STAGE_RECORDS  fused path, FP32 staging: copy the LDS footprints
+ *                     as 16-byte patch records rather than as the caller's
+ *                     pixels in FP32 (from which each update then forms its
+ *                     patch with the staging copy's own FP32 operations).
+ *                     Bit-identical.
  *   BP_OPT_POISON_STAGING  testing aid, fused path: fill each pass's staging copy
  *                     with NaN before the views are staged into it, and (LDS
  *                     stage, z_unroll 8 only; other z-unrolls: BP_ERR_UNSUPPORTED)
@@ -227,20 +232,20 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
 #define BP_OPT_STAGE_RECORDS (1 << 12)
 #define BP_OPT_POISON_STAGING (1 << 13)
 #define BP_OPT_SINGLE_TAPS (1 << 14)
+#define BP_OPT_COMPACT_STAGING (1 << 15)
 bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* Fused path with LDS staging: of every 8 consecutive views of a pass, how many
  * read their taps directly through L1 instead of from the LDS stage (0..8);
- * -1 restores the tuned share (4 for FP32 records or pixels, 3 for compact records).
+ * -1 restores the tuned share (1 for pixel stages, 4 for FP32 record stages, 3 for compact records).
  * Results are bit-identical for every share. */
 bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
 
 /* The choices the next call of size nx*ny*nz with n_views views will use; any output may be NULL.
  * direct_taps: 1 if the fused pass reads every tap through L1 (no LDS stage) -- set by
- * BP_OPT_DIRECT_TAPS, or chosen on boxes of 2e8 voxels or more for FP32 projections staged as
- * records (BP_OPT_STAGE_RECORDS, or 16-bit input with BP_OPT_WIDE_STAGING) unless a tap split
- * is set.  FP32 projections staged as pixels (the default) keep the stage, with K = 128 on
- * boxes of 2e8 voxels or more. */
+ * BP_OPT_DIRECT_TAPS, or chosen on boxes of 2e8 voxels or more for FP32 staging as records
+ * (BP_OPT_STAGE_RECORDS) unless a tap split is set.  Pixel stages (the default) and compact
+ * records keep the stage, with K = 128. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
                         bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x, int *direct_taps);
 

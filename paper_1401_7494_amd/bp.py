@@ -196,14 +196,16 @@ class Context:
     OPT_STAGE_RECORDS = 1 << 12
     OPT_POISON_STAGING = 1 << 13
     OPT_SINGLE_TAPS = 1 << 14
+    OPT_COMPACT_STAGING = 1 << 15
     ORDERS = ("region", "plain", "zslices")
 
     def set_options(self, no_cull: bool = False, no_column: bool = False, wide_staging: bool = False,
                     order: str = "region", region_ax: int = 0, direct_taps: bool = False,
                     staging: str = "auto", stage_records: bool = False, poison_staging: bool = False,
-                    single_taps: bool = False):
+                    single_taps: bool = False, compact_staging: bool = False):
         """Switch off the clipping mask or the column specialisation (on by default); stage 16-bit
-        projections as FP32 coefficients; choose the tile order ("region": XCD-private regions of
+        projections as compact FP16 coefficients (``compact_staging``) instead of as FP32 projections
+        (the default, which ``wide_staging`` names); choose the tile order ("region": XCD-private regions of
         each z-layer, ``region_ax`` regions along x (0 = default); "plain"; "zslices"); read every tap
         of the fused path directly instead of staging most views' footprints through LDS; stage the
         next pass while one runs ("overlap"), just before it ("serial") or as tuned ("auto":
@@ -233,6 +235,8 @@ class Context:
             flags |= self.OPT_POISON_STAGING
         if single_taps:
             flags |= self.OPT_SINGLE_TAPS
+        if compact_staging:
+            flags |= self.OPT_COMPACT_STAGING
         self._check(lib().bp_set_options(self._h, flags), "bp_set_options")
 
     def set_tap_split(self, direct_eighths: int = -1):

@@ -182,6 +182,14 @@ bp_status drain_timing(bp_ctx ctx)
 
 // Does the fused path stage its taps through LDS?  (The footprint table packs padded rows
 // and columns into 16 bits.)
+// 16-bit projections staged as compact FP16 records (on request; by default they are staged like
+// FP32 projections, their pixels widened exactly).
+bool compact_records(const bp_ctx_s* ctx)
+{
+    return ctx->cfg.proj_dtype != BP_F32 && (ctx->options & BP_OPT_COMPACT_STAGING) &&
+           !(ctx->options & BP_OPT_WIDE_STAGING);
+}
+
 bool staged_taps(const bp_ctx_s* ctx, bp::Layout layout, int W, int H)
 {
     return layout != bp::Layout::Checked && !(ctx->options & BP_OPT_DIRECT_TAPS) && W + 2 < 65536 && H + 2 < 65536;
@@ -214,8 +222,8 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     // measured at 1248 x 960 pixels and a 256 mm field of view, that split is ahead at L = 512
     // and behind from L = 640 up.  Compact records, and FP32 footprints staged as pixels, favour
     // the split at every size measured (pixels at L = 1024: 2675 GUPS against 2396 direct).
-    const bool compact = ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING);
-    const bool pixels = ctx->cfg.proj_dtype == BP_F32 && !(ctx->options & BP_OPT_STAGE_RECORDS);
+    const bool compact = compact_records(ctx);
+    const bool pixels = !compact && !(ctx->options & BP_OPT_STAGE_RECORDS);
     const double voxels = (double)nx * (double)ny * (double)nz;
     p.direct_taps = p.path == BP_PATH_FUSED &&
                     ((ctx->options & BP_OPT_DIRECT_TAPS) ||
@@ -224,8 +232,9 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     if (p.k <= 0) {
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
         else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
-        // LDS-staged taps, measured at 496 views: K = 64 at L = 512, 128 at L = 1024 (+4%)
-        else p.k = compact || (pixels && voxels >= 2.0e8) ? 128 : 64;
+        // LDS-staged taps, measured at 496 views: K = 128 (L = 512, FP32 pixels at 1 of 8 views
+        // direct: 2342 GUPS against 2305 at K = 64; L = 1024: +4%)
+        else p.k = 128;
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;
@@ -264,7 +273,7 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     const int W = ctx->cfg.det_width, H = ctx->cfg.det_height;
     c.plan = plan_for(ctx, nx, ny, nz, n_views);
     c.layout = c.plan.path == BP_PATH_FUSED ? bp::Layout::Patch : bp::Layout::Checked;
-    if (c.layout == bp::Layout::Patch && ctx->cfg.proj_dtype != BP_F32 && !(ctx->options & BP_OPT_WIDE_STAGING))
+    if (c.layout == bp::Layout::Patch && compact_records(ctx))
         c.layout = bp::Layout::Patch16;
     // LDS-staged taps: the footprint table packs padded rows and columns into 16 bits
     c.lds = !c.plan.direct_taps && staged_taps(ctx, c.layout, W, H);
@@ -276,9 +285,9 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     // compact records only (L = 512, 496 views: BF16 2068 -> 2151 GUPS); the FP32 staging kernel
     // contends with the pass for the vector memory path, and the pass slows by what the overlap hides.
     c.staged = c.layout != bp::Layout::Checked;
-    // FP32 input: the LDS stage holds the caller's pixels (a quarter of the bytes of the records)
-    c.raw_stage = c.lds && c.layout == bp::Layout::Patch && ctx->cfg.proj_dtype == BP_F32 &&
-                  !(ctx->options & BP_OPT_STAGE_RECORDS);
+    // FP32 records (FP32 input, or 16-bit input with wide staging): the LDS stage holds the caller's
+    // pixels as FP32 (a quarter of the bytes of the records)
+    c.raw_stage = c.lds && c.layout == bp::Layout::Patch && !(ctx->options & BP_OPT_STAGE_RECORDS);
     // share of the views of each 8 that read directly while the others are staged (tuned at L = 512,
     // 496 views: FP32 pixel stages 1, 2342 GUPS against 2313 at 2 and 2297 with every view staged;
     // FP32 record stages 4; compact records 3)
@@ -480,13 +489,15 @@ bp_status bp_set_options(bp_ctx ctx, int options)
     if (!ctx) return BP_ERR_INVALID_ARG;
     if (options & ~(BP_OPT_NO_CULL | BP_OPT_NO_COLUMN | BP_OPT_XCD_ORDER | BP_OPT_WIDE_STAGING | BP_OPT_PLAIN_ORDER |
                     BP_OPT_XCD_REGION_MASK | BP_OPT_DIRECT_TAPS | BP_OPT_SERIAL_STAGING | BP_OPT_OVERLAP_STAGING |
-                    BP_OPT_STAGE_RECORDS | BP_OPT_POISON_STAGING | BP_OPT_SINGLE_TAPS))
+                    BP_OPT_STAGE_RECORDS | BP_OPT_POISON_STAGING | BP_OPT_SINGLE_TAPS | BP_OPT_COMPACT_STAGING))
         return fail(ctx, BP_ERR_INVALID_ARG, "unknown option bits");
     const int ax = (options & BP_OPT_XCD_REGION_MASK) >> BP_OPT_XCD_REGION_SHIFT;
     if (ax != 0 && ax != 1 && ax != 2 && ax != 4 && ax != 8)
         return fail(ctx, BP_ERR_INVALID_ARG, "XCD region split must be 1, 2, 4 or 8 along x");
     if ((options & BP_OPT_SERIAL_STAGING) && (options & BP_OPT_OVERLAP_STAGING))
         return fail(ctx, BP_ERR_INVALID_ARG, "staging cannot be both serial and overlapped");
+    if ((options & BP_OPT_COMPACT_STAGING) && (options & BP_OPT_WIDE_STAGING))
+        return fail(ctx, BP_ERR_INVALID_ARG, "staging cannot be both compact and wide");
     ctx->options = options;
     return BP_OK;
 }
@@ -632,8 +643,7 @@ bp_status bp_backproject_box(bp_ctx ctx, float* volume, int nx, int ny, int nz, 
             e = timed(ctx, 0, s, [&] {
                 return bp::launch_backproject(dt, layout, plan.zu, plan.tx, volume, box, ctx->d_views + k0, kc,
                                               pad, W, H, cull, xcd_order, inv_scale, fp,
-                                              raw_stage ? static_cast<const float*>(src_views) : nullptr, s,
-                                              poison && lds);
+                                              raw_stage ? src_views : nullptr, s, poison && lds);
             });
             if (e == hipSuccess && overlap && hipEventRecord(ctx->ev_done[half], s) != hipSuccess)
                 return fail(ctx, BP_ERR_LAUNCH, "cannot record the end of a pass");

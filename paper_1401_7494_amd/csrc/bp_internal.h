@@ -86,15 +86,15 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 // footprints (patch layouts only; null = read the taps directly): the pass's
 // footprint table from launch_footprint, [tile][view] -- the taps are then
 // staged through LDS.  raw (Layout::Patch with footprints only; else null): the
-// caller's FP32 images of the pass, [n][H][W] -- staged footprints are then
-// copied into LDS as pixels (footprint table made with raw = true).  poison (LDS-staged passes
+// caller's images of the pass (of type dt), [n][H][W] -- staged footprints are then
+// copied into LDS as FP32 pixels (footprint table made with raw = true).  poison (LDS-staged passes
 // with z_unroll 8 only): fill the LDS stage with NaN before each staged footprint (testing aid).
 // single_taps (caller's FP32 images): one dword load per tap instead of one 8-byte load per
 // pixel pair.
 hipError_t launch_backproject(Dtype dt, Layout layout, int z_unroll, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H,
                               const Cull& cull, int xcd_order, const float* inv_scale, const uint2* footprints,
-                              const float* raw, hipStream_t s, bool poison = false, bool single_taps = false);
+                              const void* raw, hipStream_t s, bool poison = false, bool single_taps = false);
 
 // Fill `bytes` (a multiple of 4) with copies of a 32-bit word (a kernel, not a memset node).
 hipError_t launch_fill(void* p, size_t bytes, uint32_t word, hipStream_t s);

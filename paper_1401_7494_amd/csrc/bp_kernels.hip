@@ -366,16 +366,21 @@ struct PatchSource {
     }
 };
 
-// FP32 projections: directly read views take patch records as PatchSource
-// does; a staged footprint is copied into LDS as the caller's FP32 pixels (a
-// quarter of the bytes of its records), and each update forms its patch's
-// coefficients from the four pixels with the same FP32 operations as
-// patch_kernel, so both paths give the same bits.
-struct RawPatchSource : PatchSource {
-    const float* raw;  // the caller's images of the pass, [n][H][W]
-    static constexpr bool kRawStage = true;
+// Pixel stages: directly read views take FP32 patch records as PatchSource
+// does; a staged footprint is copied into LDS as the caller's pixels, in FP32
+// (a quarter of the bytes of its records; 16-bit pixels convert exactly), and
+// each update forms its patch's coefficients from the four pixels with the
+// same FP32 operations as patch_kernel, so both paths give the same bits.
+__device__ short raw_buffer_load_i16(i32x4_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.i16");
 
-    // View k's pixels as a byte-addressed buffer of W H FP32 values: offsets past the end read 0
+template <typename T>
+struct RawPatchSource : PatchSource {
+    const T* raw;  // the caller's images of the pass, [n][H][W]
+    static constexpr bool kRawStage = true;
+    static constexpr uint32_t kElem = sizeof(T);
+
+    // View k's pixels as a byte-addressed buffer of W H values: offsets past the end read 0
     // (the buffer's range check; no memory access).
     __device__ __forceinline__ i32x4_t raw_view(int k) const
     {
@@ -383,16 +388,26 @@ struct RawPatchSource : PatchSource {
         i32x4_t rs;
         rs.x = (int)(uint32_t)a;
         rs.y = (int)((uint32_t)(a >> 32) & 0xffffu);
-        rs.z = (int)((uint32_t)W * (uint32_t)H * 4u);
+        rs.z = (int)((uint32_t)W * (uint32_t)H * kElem);
         rs.w = 0x00020000;
         return rs;
     }
 
-    // The record of padded patch (r0, c0) (c0 in [0, W + 1], r0 in [0, H + 1]) from the view's
-    // pixels, zero off the detector, with the operations of patch_kernel.  Every tap is read at an
-    // index clamped into the image and zeroed by a select when it lies off the detector.  (The
-    // buffer's range check is not relied on here: the compiler merges the loads of two adjacent
-    // pixels into one 8-byte load, which is out of range as a whole when its first pixel is.)
+    // The bits of the pixel at byte offset `off` of a view (0 past the view's end), and their FP32
+    // value.  The prefetch keeps the bits, so that no conversion waits on a load in flight.
+    static __device__ __forceinline__ uint32_t raw_bits(const i32x4_t& rs, int off)
+    {
+        if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, raw_buffer_load_f32(rs, off, 0, 0));
+        else return (uint16_t)raw_buffer_load_i16(rs, off, 0, 0);
+    }
+    static __device__ __forceinline__ float from_bits(uint32_t b)
+    {
+        if constexpr (sizeof(T) == 4) return u32_as_f32(b);
+        else if constexpr (__is_same(T, __half)) return f16_lo(b);
+        else return bf16_lo(b);
+    }
+    static __device__ __forceinline__ float raw_tap(const i32x4_t& rs, int off) { return from_bits(raw_bits(rs, off)); }
+
     __device__ __forceinline__ Rec raw_rec(const i32x4_t& rs, int c0, int r0) const
     {
         const int i = c0 - 1, j = r0 - 1;
@@ -400,8 +415,9 @@ struct RawPatchSource : PatchSource {
         const bool ra = (unsigned)j < (unsigned)H, rb = (unsigned)(j + 1) < (unsigned)H;
         const int ia = min(max(i, 0), W - 1), ib = min(i + 1, W - 1);
         const int ja = min(max(j, 0), H - 1) * W, jb = min(j + 1, H - 1) * W;
-        const float a0 = raw_buffer_load_f32(rs, (ja + ia) * 4, 0, 0), b0 = raw_buffer_load_f32(rs, (ja + ib) * 4, 0, 0);
-        const float c1 = raw_buffer_load_f32(rs, (jb + ia) * 4, 0, 0), d1 = raw_buffer_load_f32(rs, (jb + ib) * 4, 0, 0);
+        const int e = (int)kElem;
+        const float a0 = raw_tap(rs, (ja + ia) * e), b0 = raw_tap(rs, (ja + ib) * e);
+        const float c1 = raw_tap(rs, (jb + ia) * e), d1 = raw_tap(rs, (jb + ib) * e);
         const float a = (ra & ca) ? a0 : 0.0f, b = (ra & cb) ? b0 : 0.0f;
         const float cc = (rb & ca) ? c1 : 0.0f, d = (rb & cb) ? d1 : 0.0f;
         Rec q;
@@ -707,10 +723,12 @@ __global__ __launch_bounds__(kBlock, PADDED ? 1 : 8) void backproject_kernel(
 template <class Src, bool RAW = Src::kRawStage>
 struct StageOf {
     using type = typename Src::Rec;  // what the stage holds: records
+    using pre = type;
 };
 template <class Src>
 struct StageOf<Src, true> {
-    using type = float;  // the stage: the footprint's pixels
+    using type = float;     // the stage: the footprint's pixels
+    using pre = uint32_t;   // their bits as loaded
 };
 
 
@@ -733,7 +751,7 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
     constexpr bool kRaw = Src::kRawStage;
     static_assert(kStageMaxWidth * kStageMaxHeight == kStageRecords, "LDS stage shape");
     using StageT = typename StageOf<Src>::type;  // patch records, or FP32 pixels
-    using PreT = StageT;  // what a lane prefetches
+    using PreT = typename StageOf<Src>::pre;     // what a lane prefetches: records, or pixel bits
     __shared__ StageT lds[kRaw ? kRawStride * kRawRows : kStageRecords];
     constexpr int TY = kBlock / TX;
     const int gx = (box.nx + TX - 1) / TX, gy = (box.ny + TY - 1) / TY, gz = (box.nz + ZU - 1) / ZU;
@@ -768,24 +786,27 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
-            // Padded pixel (r, c) is detector pixel (c - 1, r - 1), at byte offset ((r - 1) W + c - 1) 4
-            // of the view.  A pixel off the detector is read at an offset past the view's W H 4 < 2^31
-            // bytes, which the buffer's range check returns as 0 without a memory access: columns off
-            // the detector at kFar and beyond, rows below it past the end by themselves, the row above
-            // it (slot 0 of wave 0 when rmin = 0) at kFar.  No offset wraps in 32 bits (W <= 2^20).
+            // Padded pixel (r, c) is detector pixel (c - 1, r - 1), at byte offset ((r - 1) W + c - 1) e
+            // of the view (e bytes per pixel).  A pixel off the detector is read at an offset past the
+            // view's W H e < 2^31 bytes, which the buffer's range check returns as 0 without a memory
+            // access: columns off the detector at kFar and beyond, rows below it past the end by
+            // themselves, the row above it (slot 0 of wave 0 when rmin = 0) at kFar.  No offset wraps
+            // in 32 bits (W <= 2^20).  Each lane loads one pixel per slot (no two of its loads are
+            // adjacent, so none is merged into a wider load).
             constexpr uint32_t kFar = 0xC0000000u;
+            constexpr uint32_t e = Src::kElem;
             const int c = cmin + lane;
             const bool col_ok = (lane <= fw) & (c >= 1) & (c <= src.W);
-            const uint32_t row_bytes = (uint32_t)src.W * 4u;
+            const uint32_t row_bytes = (uint32_t)src.W * e;
             // slot 1's row, rmin + 3 + wave >= 3, is never above the detector
-            const uint32_t off1 = col_ok ? (uint32_t)(rmin + 3 + wave) * row_bytes + (uint32_t)(c - 1) * 4u : kFar;
+            const uint32_t off1 = col_ok ? (uint32_t)(rmin + 3 + wave) * row_bytes + (uint32_t)(c - 1) * e : kFar;
             const i32x4_t rs = src.raw_view(k);
             if (wave <= fh)
-                pre[0] = raw_buffer_load_f32(rs, (int)(rmin - 1 + wave >= 0 ? off1 - 4u * row_bytes : kFar), 0, 0);
+                pre[0] = Src::raw_bits(rs, (int)(rmin - 1 + wave >= 0 ? off1 - 4u * row_bytes : kFar));
 #pragma unroll
             for (int j = 1; j < kSlots; ++j)
                 if (wave + 4 * j <= fh)
-                    pre[j] = raw_buffer_load_f32(rs, (int)(off1 + (uint32_t)(4 * (j - 1)) * row_bytes), 0, 0);
+                    pre[j] = Src::raw_bits(rs, (int)(off1 + (uint32_t)(4 * (j - 1)) * row_bytes));
         } else {
             const auto vw = src.view(k);
             const int cols = src.cols();
@@ -805,7 +826,7 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
                 StageT* dst = buf + wave * kRawStride + lane;
 #pragma unroll
                 for (int j = 0; j < kSlots; ++j)
-                    if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = pre[j];
+                    if (wave + 4 * j <= fh) dst[4 * j * kRawStride] = Src::from_bits(pre[j]);
             }
         } else {
             if (lane < fw) {
@@ -1547,23 +1568,32 @@ hipError_t launch_patch16(Dtype dt, const void* proj, int W, int H, int n, void*
 
 hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float* vol, const Box& box,
                               const ViewConst* vc, int n, const void* src, int W, int H, const Cull& cl,
-                              int xcd_order, const float* inv_scale, const uint2* fp, const float* raw,
+                              int xcd_order, const float* inv_scale, const uint2* fp, const void* raw,
                               hipStream_t s, bool poison, bool single_taps)
 {
     const uint8_t* base = (const uint8_t*)src;
     if (fp && raw && layout == Layout::Patch) {
-        RawPatchSource ps;
-        ps.base = base;
-        ps.W = W;
-        ps.H = H;
-        ps.raw = raw;
-        switch (tile_x) {
-        case 64: return launch_zu_lds<RawPatchSource, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
-        case 32: return launch_zu_lds<RawPatchSource, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
-        case 16: return launch_zu_lds<RawPatchSource, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
-        case 8: return launch_zu_lds<RawPatchSource, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
-        default: return hipErrorInvalidValue;
+        auto go = [&](auto tag) -> hipError_t {
+            using T = decltype(tag);
+            RawPatchSource<T> ps;
+            ps.base = base;
+            ps.W = W;
+            ps.H = H;
+            ps.raw = static_cast<const T*>(raw);
+            switch (tile_x) {
+            case 64: return launch_zu_lds<RawPatchSource<T>, 64>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+            case 32: return launch_zu_lds<RawPatchSource<T>, 32>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+            case 16: return launch_zu_lds<RawPatchSource<T>, 16>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+            case 8: return launch_zu_lds<RawPatchSource<T>, 8>(zu, vol, box, vc, n, ps, fp, xcd_order, poison, s);
+            default: return hipErrorInvalidValue;
+            }
+        };
+        switch (dt) {
+        case Dtype::F32: return go(float{});
+        case Dtype::F16: return go(__half{});
+        case Dtype::BF16: return go(uint16_t{});
         }
+        return hipErrorInvalidValue;
     }
     if (raw) return hipErrorInvalidValue;  // pixels are staged for FP32 records only
     if (fp && layout == Layout::Patch16) {

@@ -56,7 +56,7 @@ def product_matrices(scanner):
 
 
 def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0, zu=0, init=None,
-            stream=None, tx=0, wide_staging=None, cubic=False):
+            stream=None, tx=0, compact=False, cubic=False):
     """Back project on cuda:0 through the C ABI; returns the volume as a float32 numpy array."""
     dev = torch.device("cuda:0")
     nz, ny, nx = shape
@@ -65,11 +65,9 @@ def run_gpu(proj, P32, shape, voxel_size, origin, dtype="f32", path="auto", k=0,
     p = proj.to(dev).contiguous() if isinstance(proj, torch.Tensor) else torch.from_numpy(proj).to(dev)
     m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
     H, W = p.shape[1:]
-    if wide_staging is None:  # exact FP32 coefficients unless the caller asks for the compact form
-        wide_staging = True
-    with bp.Context(W, H, dtype) as ctx:
+    with bp.Context(W, H, dtype) as ctx:  # FP32 staging unless the caller asks for the compact form
         ctx.set_tuning(path, k, zu, tx)
-        ctx.set_options(wide_staging=wide_staging)
+        ctx.set_options(compact_staging=compact)
         ctx.backproject(vol, p, m, voxel_size, origin, stream, cubic=cubic)
         torch.cuda.synchronize()
     return vol.cpu().numpy()

@@ -208,7 +208,7 @@ def test_invalid_arguments_enqueue_nothing():
         assert L.bp_set_tuning(h, 9, 0, 0, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 3, 0) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_tuning(h, 0, 0, 0, 12) == bp.BP_ERR_INVALID_ARG
-        assert L.bp_set_options(h, 1 << 15) == bp.BP_ERR_INVALID_ARG
+        assert L.bp_set_options(h, 1 << 16) == bp.BP_ERR_INVALID_ARG
         assert L.bp_set_options(h, 3 << 5) == bp.BP_ERR_INVALID_ARG  # region split of 3 along x
         assert L.bp_set_options(h, (1 << 10) | (1 << 11)) == bp.BP_ERR_INVALID_ARG  # serial and overlapped
         torch.cuda.synchronize()
@@ -241,11 +241,11 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
-        # staged or direct taps: FP32 pixel stages at every size (K = 128 on large grids); FP32
-        # record stages at L = 512, direct reads on finer, larger grids
+        # staged or direct taps: FP32 pixel stages at every size (K = 128); FP32 record stages at
+        # L = 512, direct reads on finer, larger grids
         ctx.set_tuning("auto", 0, 0, 0)
         p = ctx.plan(512, 512, 512, 496)
-        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, False)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
         p = ctx.plan(1024, 1024, 1024, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
         ctx.set_options(stage_records=True)
@@ -320,7 +320,7 @@ def test_parity_l512_sampled(dtype, compact, path):
     A = sum_k |contribution_k| (the oracle's magnitude mode; FP32 accumulation error scales with
     A, not with V where signed contributions cancel), and a block conditioned like the volume
     (A / V at most twice the volume's) is held to its own relative L2 too.  16-bit inputs are
-    compared with the oracle on the same rounded values, with FP32 (wide) staging at the 1e-5
+    compared with the oracle on the same rounded values, with FP32 staging (the default) at the 1e-5
     bar and with compact FP16 staging at its derived bar."""
     wl = synth.WORKLOADS["fdk_l512_v496_f32"]
     v = wl.volume
@@ -328,8 +328,7 @@ def test_parity_l512_sampled(dtype, compact, path):
     max_tol = gc.COMPACT_MAX_ABS_TOL if compact else gc.MAX_ABS_TOL
     proj = gc.full_projections(wl.phantom_seed).to(gc.TORCH_DTYPE[dtype])
     P32 = gc.product_matrices(wl.scanner)
-    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype, wide_staging=not compact,
-                     path=path)
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype, compact=compact, path=path)
     proj_np = proj.float().cpu().numpy()
     P64 = P32.astype(np.float64)
     xyz = strided_sample(v.L, 8, 3)
@@ -398,7 +397,7 @@ def test_parity_l512_tilted_orbit_sampled():
 
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
-              order="region", region_ax=0, direct_taps=False, wide_staging=False, tap_split=-1,
+              order="region", region_ax=0, direct_taps=False, compact=False, tap_split=-1,
               staging="auto", stage_records=False, poison=False):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
@@ -408,7 +407,7 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning("fused", k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
-                        direct_taps=direct_taps, wide_staging=wide_staging, staging=staging,
+                        direct_taps=direct_taps, compact_staging=compact, staging=staging,
                         stage_records=stage_records, poison_staging=poison)
         ctx.set_tap_split(tap_split)
         ctx.backproject(vol, p, m, vs, origin)
@@ -528,8 +527,8 @@ def test_tile_shapes_and_block_order(small_inputs, tx, zu):
     assert gc.rel_l2(a, ref) <= gc.REL_L2_TOL
 
 
-@pytest.mark.parametrize("dtype,wide", [("f32", False), ("f16", False), ("bf16", False), ("bf16", True)])
-def test_lds_staged_taps_are_bit_identical(dtype, wide):
+@pytest.mark.parametrize("dtype,compact", [("f32", False), ("f16", True), ("bf16", True), ("bf16", False), ("f16", False)])
+def test_lds_staged_taps_are_bit_identical(dtype, compact):
     """Taps staged through LDS per (tile, view) footprint give the same bits as direct taps, for any
     share of views read directly and with FP32 footprints staged as pixels or as records: column and
     general branches, culled tiles, guarded views (direct inside the staged pass), footprints too
@@ -546,10 +545,10 @@ def test_lds_staged_taps_are_bit_identical(dtype, wide):
     for shape, vs, kw in cases:
         origin = _box_origin(shape, vs)
         for tx, zu in ((16, 8), (64, 1), (8, 4)):
-            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
+            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, compact=compact,
                           direct_taps=True, **kw)
             for split in (-1, 0, 5):  # tuned share of direct views, all staged, 5 of 8 direct
-                b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, wide_staging=wide,
+                b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=13, zu=zu, tx=tx, compact=compact,
                               tap_split=split, **kw)
                 assert np.array_equal(a, b), (shape, vs, kw, tx, zu, split)
             if dtype == "f32":  # FP32 footprints staged as records instead of pixels
@@ -583,9 +582,9 @@ def test_pixel_stage_at_the_detector_corners():
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
 
 
-@pytest.mark.parametrize("dtype,wide,records", [("f32", False, False), ("f32", False, True), ("bf16", False, False),
-                                                ("bf16", True, False)])
-def test_poisoned_staging_changes_nothing(dtype, wide, records):
+@pytest.mark.parametrize("dtype,compact,records", [("f32", False, False), ("f32", False, True), ("bf16", True, False),
+                                                   ("bf16", False, False)])
+def test_poisoned_staging_changes_nothing(dtype, compact, records):
     """The staging copy of each pass and the LDS stage of each footprint filled with NaN before
     they are written: the result is finite and bit-identical, so no element the staging did not
     write is ever read -- records of views only some tiles read directly, unused LDS rows and
@@ -604,7 +603,7 @@ def test_poisoned_staging_changes_nothing(dtype, wide, records):
         o = _box_origin(shape, vs)
         origin = (o[0] + shift[0], o[1] + shift[1], o[2] + shift[2])
         for split, staging in ((-1, "serial"), (0, "overlap"), (5, "serial")):
-            kw = dict(dtype=dtype, k=13, zu=8, tx=16, wide_staging=wide, stage_records=records, tap_split=split,
+            kw = dict(dtype=dtype, k=13, zu=8, tx=16, compact=compact, stage_records=records, tap_split=split,
                       staging=staging)
             a = _run_opts(proj, P32, shape, vs, origin, **kw)
             b = _run_opts(proj, P32, shape, vs, origin, poison=True, **kw)
@@ -613,8 +612,8 @@ def test_poisoned_staging_changes_nothing(dtype, wide, records):
             assert np.abs(a).max() > 0
 
 
-@pytest.mark.parametrize("dtype,wide", [("f32", False), ("bf16", False), ("bf16", True)])
-def test_staging_overlap_is_bit_identical(dtype, wide):
+@pytest.mark.parametrize("dtype,compact", [("f32", False), ("bf16", True), ("bf16", False)])
+def test_staging_overlap_is_bit_identical(dtype, compact):
     """Staging the next pass on the context's side stream while the current pass runs gives the same
     bits as staging each pass just before it: many passes (both halves of the staging buffer reused),
     a ragged last pass, LDS-staged and direct taps, and a caller on a non-default stream whose earlier
@@ -628,9 +627,9 @@ def test_staging_overlap_is_bit_identical(dtype, wide):
     origin = _box_origin(shape, vs)
     for k in (4, 13, 28):  # 8, 3 and 2 passes
         for direct in (False, True):
-            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, wide_staging=wide,
+            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, compact=compact,
                           direct_taps=direct, staging="serial")
-            b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, wide_staging=wide,
+            b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=k, zu=8, tx=16, compact=compact,
                           direct_taps=direct, staging="overlap")
             assert np.array_equal(a, b), (k, direct)
             assert np.abs(a).max() > 0
@@ -644,7 +643,7 @@ def test_staging_overlap_is_bit_identical(dtype, wide):
         st = torch.cuda.current_stream(dev) if serial else torch.cuda.Stream(device=dev)
         with bp.Context(sc.W, sc.H, dtype) as ctx:
             ctx.set_tuning("fused", 4, 8, 16)
-            ctx.set_options(wide_staging=wide, staging="serial" if serial else "overlap")
+            ctx.set_options(compact_staging=compact, staging="serial" if serial else "overlap")
             vol = torch.zeros(shape, dtype=torch.float32, device=dev)
             torch.cuda.synchronize()
             with torch.cuda.stream(st):
@@ -663,15 +662,13 @@ def test_staging_overlap_is_bit_identical(dtype, wide):
 def test_compact_staging_within_fp16_bound(small_inputs, dtype, tx, zu):
     """Compact staging (FP16 patch coefficients, per-view power-of-two scale) against the
     oracle on the same rounded data, within the bar derived from FP16 rounding of the
-    pixel differences; wide staging of the same data meets the FP32 bar."""
+    pixel differences; FP32 staging (the default) of the same data meets the FP32 bar."""
     proj32, P32 = small_inputs
     proj = proj32.to(gc.TORCH_DTYPE[dtype]) * 1000.0  # large values: the per-view scale must engage
     origin = _box_origin(BOX, VS)
     ref = _oracle_box(proj, P32, BOX, VS, origin)
-    compact = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx,
-                         wide_staging=False)
-    wide = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx,
-                      wide_staging=True)
+    compact = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx, compact=True)
+    wide = gc.run_gpu(proj, P32, BOX, VS, origin, dtype=dtype, path="fused", k=6, zu=zu, tx=tx)
     e_c, e_w = gc.error_stats(compact, ref), gc.error_stats(wide, ref)
     print(f"\n{dtype} compact: {e_c}\n{dtype} wide: {e_w}")
     assert e_w["rel_l2"] <= gc.REL_L2_TOL

@@ -76,20 +76,22 @@ def kernel_source_sha():
 
 
 def counter_record(kernel: str, launch: str, workload: str):
-    """The committed rocprofv3 counter record of this kernel, launch and workload, or None when the
-    kernel sources changed since it was taken (or it is for another kernel or launch)."""
+    """The committed rocprofv3 counter record of this kernel, launch and workload (the file holds one
+    per profiled launch), or None when the kernel sources changed since it was taken or no record is
+    for this kernel and launch."""
     path = os.path.join(ROOT, COUNTERS_MD)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     if "```json" not in text:
         return None
-    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    if rec.get("kernel_source_sha256") != kernel_source_sha() or rec.get("kernel") != kernel:
-        return None
-    if rec.get("launch_key") != launch or rec.get("workload") != workload:
-        return None
-    return rec
+    recs = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    sha = kernel_source_sha()
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if (rec.get("kernel_source_sha256") == sha and rec.get("kernel") == kernel and
+                rec.get("launch_key") == launch and rec.get("workload") == workload):
+            return rec
+    return None
 
 
 def parse():
@@ -115,6 +117,7 @@ def parse():
     ap.add_argument("--cpu-block", type=int, default=320,
                     help="edge of the centre block the oracle times (about 10 s of FP64 work on 16 threads)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-clocks", action="store_true", help="do not query clocks with rocm-smi (profiled runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     return ap.parse_args()
@@ -126,8 +129,13 @@ def device_info(torch):
             "compute_units": p.multi_processor_count, "memory_gib": round(p.total_memory / 2 ** 30, 1)}
 
 
+NO_CLOCKS = False  # --no-clocks: under a profiler, whose preloaded library makes the query's exec fail
+
+
 def clocks():
     """Current shader and memory clocks as rocm-smi reports them (None if it cannot)."""
+    if NO_CLOCKS:
+        return None
     try:
         out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
         data = json.loads(out.stdout[out.stdout.index("{"):])
@@ -352,7 +360,8 @@ def headline(b: Bench, res: dict):
         plan = b.plan_of(ctx, v, sc.n_views)
         step_ms, kern, vol = b.run(ctx, proj, P, v, args.steps, args.warmup)
         ctx.close()
-        r = {**plan, "dtype": dt, **stats(step_ms, updates), "kernels": kern, "tuning": tuning}
+        r = {**plan, "dtype": dt, **stats(step_ms, updates), "kernels": kern, "tuning": tuning,
+             "tap_split": tuning["tap_split"] if tuning else args.tap_split}
         log(f"bench: {form}: {r['ms_per_step']} ms/step, p50 {r['gups_p50']} GUPS, plan {plan}, kernels {kern}")
         out[form] = r
         vols[form] = vol
@@ -417,7 +426,10 @@ def headline(b: Bench, res: dict):
     else:
         kernel = "backproject_kernel"
     k = head["views_per_pass"]
-    launch = f"K={k} ZU={head['z_unroll']} TX={head['tile_x']} split={(head.get('tuning') or {}).get('tap_split', -1)}"
+    split = head["tap_split"]
+    if split < 0 and kernel == "backproject_lds_kernel":
+        split = 1  # the library's share of directly read views for FP32 pixel stages
+    launch = f"K={k} ZU={head['z_unroll']} TX={head['tile_x']} split={split}"
     rec = counter_record(kernel, launch, wl.name)
     views_per_launch = upl / float(v.L) ** 3
     alg_bytes = upl * (8.0 / views_per_launch + sc.W * sc.H * 4.0 / float(v.L) ** 3)
@@ -794,6 +806,8 @@ def leg_c5(b: Bench):
 
 def main():
     args = parse()
+    global NO_CLOCKS
+    NO_CLOCKS = args.no_clocks
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (sharding the volume into z-slabs "
               "across GPUs is designed but not implemented)", file=sys.stderr)

@@ -83,8 +83,8 @@ typedef enum {
                            the caller's images with per-tap bounds (no staging copy):
                            for volumes small next to the projections, where writing
                            the staging copy would cost more than the taps save.
-                           BP_PATH_AUTO takes it when the box has fewer than 8 x W x H
-                           voxels */
+                           BP_PATH_AUTO takes it when the box has fewer than 64 x W x H
+                           voxels for FP32 projections (8 x W x H for 16-bit ones) */
 } bp_path;
 
 typedef struct {

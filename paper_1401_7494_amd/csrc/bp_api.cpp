@@ -210,12 +210,15 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     Plan p;
     p.path = ctx->path_override != BP_PATH_AUTO ? ctx->path_override : ctx->cfg.path;
     if (p.path == BP_PATH_AUTO) {
-        // the staging copy writes 16 (8) bytes per pixel of every view: for a small box that
-        // costs more than the taps it saves (measured crossover between L = 128 and 256 at
-        // 1248 x 960 pixels)
+        // Coarse voxels (few per detector pixel, so a tile's footprint overflows the LDS stage and
+        // no two voxels share a pixel) favour reading the caller's images directly.  Measured at
+        // 1248 x 960 pixels, 496 views, 256 mm field: FP32 (pixel-pair taps) direct at L = 384
+        // (1030 GUPS against 627 staged), staged at L = 448 (1762 against 1129); 16-bit input
+        // (single taps) staged at L = 256 (386 against 354).
         const double voxels = (double)nx * (double)ny * (double)nz;
-        p.path = voxels < 8.0 * ctx->cfg.det_width * (double)ctx->cfg.det_height ? BP_PATH_FUSED_DIRECT
-                                                                                  : BP_PATH_FUSED;
+        const double pixels = (double)ctx->cfg.det_width * (double)ctx->cfg.det_height;
+        const double crossover = ctx->cfg.proj_dtype == BP_F32 ? 64.0 : 8.0;
+        p.path = voxels < crossover * pixels ? BP_PATH_FUSED_DIRECT : BP_PATH_FUSED;
     }
     // Staged or direct taps for the fused pass.  FP32 records staged as records, on a fine grid
     // (many voxels per detector pixel), reuse the L1 well enough that the direct loads win:

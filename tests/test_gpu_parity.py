@@ -235,9 +235,10 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused", 500, 2, 8)
         p = ctx.plan(64, 64, 64, 496)
         assert (p.views_per_pass, p.tile_x) == (496, 8)
-        ctx.set_tuning("auto", 0, 0, 0)  # small boxes read the caller's images, large ones the staging copy
+        ctx.set_tuning("auto", 0, 0, 0)  # coarse boxes read the caller's images, fine ones the staging copy
         assert ctx.plan(128, 128, 128, 496).path == "fused_direct"
-        assert ctx.plan(256, 256, 256, 496).path == "fused"
+        assert ctx.plan(384, 384, 384, 496).path == "fused_direct"
+        assert ctx.plan(448, 448, 448, 496).path == "fused"
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
@@ -260,6 +261,7 @@ def test_plan_reports_choices():
     with bp.Context(1248, 960, "bf16") as ctx:
         p = ctx.plan(1024, 1024, 1024, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
+        assert ctx.plan(256, 256, 256, 496).path == "fused"  # 16-bit taps are single loads: staged sooner
 
 
 # ---------------------------------------------------------------------------

@@ -400,14 +400,15 @@ def test_parity_l512_tilted_orbit_sampled():
 
 def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtype="f32", k=0, zu=0, tx=0,
               order="region", region_ax=0, direct_taps=False, compact=False, tap_split=-1,
-              staging="auto", stage_records=False, poison=False):
+              staging="auto", stage_records=False, poison=False, path="fused", init=None):
     dev = torch.device("cuda:0")
-    vol = torch.zeros(shape, dtype=torch.float32, device=dev)
+    vol = torch.zeros(shape, dtype=torch.float32, device=dev) if init is None else \
+        torch.as_tensor(init, dtype=torch.float32).to(dev).contiguous()
     p = proj.to(dev).contiguous()
     m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
     n, H, W = p.shape
     with bp.Context(W, H, dtype) as ctx:
-        ctx.set_tuning("fused", k, zu, tx)
+        ctx.set_tuning(path, k, zu, tx)
         ctx.set_options(no_cull=no_cull, no_column=no_column, order=order, region_ax=region_ax,
                         direct_taps=direct_taps, compact_staging=compact, staging=staging,
                         stage_records=stage_records, poison_staging=poison)
@@ -486,6 +487,38 @@ def test_clipping_mask_is_exact_and_column_path_matches(zu):
         err = gc.error_stats(got, ref)
         print(f"\n{name} ZU={zu}: {err}")
         assert err["rel_l2"] <= gc.REL_L2_TOL, (name, err)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("path,k,tx", [("plain", 1, 16), ("plain", 1, 64), ("fused_direct", 13, 16)])
+def test_clipping_mask_on_the_caller_image_passes(path, k, tx, dtype):
+    """Passes on the caller's images skip every (tile, view) pair that misses the detector, and a
+    tile that all views of a pass miss is neither read nor written: on a volume that already holds
+    values, the result equals the pass without the mask (which adds exact zeros there) bit for bit,
+    and the oracle's sum on top of those values."""
+    sc = synth.Scanner(n_views=29, W=120, H=64, pitch=2.0)  # small detector: many tiles fall off it
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(83))
+    if dtype != "f32":
+        proj = proj.to(gc.TORCH_DTYPE[dtype])
+    P32 = gc.product_matrices(sc)
+    shape, vs = (40, 70, 130), 2.0
+    origin = _box_origin(shape, vs)
+    init = (0.01 * np.random.default_rng(83).standard_normal(shape)).astype(np.float32)
+    full = _run_opts(proj, P32, shape, vs, origin, no_cull=True, k=k, zu=8, tx=tx, dtype=dtype, path=path,
+                     init=init)
+    culled = _run_opts(proj, P32, shape, vs, origin, k=k, zu=8, tx=tx, dtype=dtype, path=path, init=init)
+    assert np.array_equal(culled, full)
+    ref = _oracle_box(proj, P32, shape, vs, origin)
+    assert gc.rel_l2(culled - init, ref) <= gc.REL_L2_TOL
+    # the box reaches beyond the detector in some views, so the mask acts: voxel centres (every 4th
+    # per axis) that project off the detector
+    nz, ny, nx = shape
+    g = [np.arange(0, n, 4) * vs + o for n, o in zip((nx, ny, nz), origin)]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel(), np.ones(X.size)])
+    uvw = np.asarray(P32, np.float64).reshape(-1, 3, 4) @ pts
+    s_, t_ = uvw[:, 0] / uvw[:, 2], uvw[:, 1] / uvw[:, 2]
+    assert ((s_ <= -1) | (s_ >= sc.W) | (t_ <= -1) | (t_ >= sc.H)).any()
 
 
 def test_column_branch_needs_exact_zeros():

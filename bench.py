@@ -18,8 +18,9 @@ baseline times.
   C1  plain FP32, L=128 (voxel 2 mm), 496 views; error over the whole volume
   C3  batched fused, L=1024 (4 GiB), 496 views streamed K per pass, K / z-unroll / tile width
       chosen by the autotuner (K over 1, 2, 4, 8, 16 and wider); sampled error
-  C4  FP16 and BF16 storage of the phantom + 1% Gaussian noise, L=512; error of the compact
-      and the wide staging against the oracle on the FP32 data and on the rounded data
+  C4  FP16 and BF16 storage of the phantom + 1% Gaussian noise, L=512; throughput and error of the
+      default FP32 staging and of the compact FP16 records, against the oracle on the FP32 data
+      and on the rounded data
   C5  the serving mix: 200 seeded requests (L in 128/256/512, 124/248/496 views, FP32/FP16),
       first all at once (capacity), then Poisson at 0.8 x capacity; p50/p99 latency,
       aggregate GUPS, ingest and back-projection device times, peak admitted HBM

@@ -429,7 +429,7 @@ def headline(b: Bench, res: dict):
     k = head["views_per_pass"]
     split = head["tap_split"]
     if split < 0 and kernel == "backproject_lds_kernel":
-        split = 1  # the library's share of directly read views for FP32 pixel stages
+        split = 0  # the library's share of directly read views for FP32 pixel stages
     launch = f"K={k} ZU={head['z_unroll']} TX={head['tile_x']} split={split}"
     rec = counter_record(kernel, launch, wl.name)
     views_per_launch = upl / float(v.L) ** 3

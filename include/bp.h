@@ -237,7 +237,7 @@ bp_status bp_set_options(bp_ctx ctx, int options);
 
 /* Fused path with LDS staging: of every 8 consecutive views of a pass, how many
  * read their taps directly through L1 instead of from the LDS stage (0..8);
- * -1 restores the tuned share (1 for pixel stages, 4 for FP32 record stages, 3 for compact records).
+ * -1 restores the tuned share (0 for pixel stages, 4 for FP32 record stages, 3 for compact records).
  * Results are bit-identical for every share. */
 bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
 

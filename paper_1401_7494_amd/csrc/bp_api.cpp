@@ -292,9 +292,9 @@ CallShape call_shape(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     // pixels as FP32 (a quarter of the bytes of the records)
     c.raw_stage = c.lds && c.layout == bp::Layout::Patch && !(ctx->options & BP_OPT_STAGE_RECORDS);
     // share of the views of each 8 that read directly while the others are staged (tuned at L = 512,
-    // 496 views: FP32 pixel stages 1, 2342 GUPS against 2313 at 2 and 2297 with every view staged;
-    // FP32 record stages 4; compact records 3)
-    c.split = ctx->tap_split >= 0 ? ctx->tap_split : (c.raw_stage ? 1 : c.layout == bp::Layout::Patch ? 4 : 3);
+    // 496 views, K = 128: pixel stages 0 -- every view staged; BF16 24.55 ms against 25.05 at 1 of 8,
+    // FP32 26.57 against 26.49; FP32 record stages 4; compact records 3)
+    c.split = ctx->tap_split >= 0 ? ctx->tap_split : (c.raw_stage ? 0 : c.layout == bp::Layout::Patch ? 4 : 3);
     c.overlap = c.staged && n_views > c.plan.k && !(ctx->options & BP_OPT_SERIAL_STAGING) &&
                 (c.layout == bp::Layout::Patch16 || (ctx->options & BP_OPT_OVERLAP_STAGING));
     c.halves = c.overlap ? 2 : 1;

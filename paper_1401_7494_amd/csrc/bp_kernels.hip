@@ -8,8 +8,10 @@
 // GPU mapping
 //   * One thread owns ZU voxels of one (x, y) column at consecutive z; a
 //     256-thread block covers TX x (256 / TX) columns (16 x 16 by default), a
-//     wavefront TX x (64 / TX), so volume loads and stores are whole row
-//     segments.  Voxels stay in registers for all the views of a pass; the
+//     wavefront TX x (64 / TX) in the passes on the caller's images (so volume
+//     loads and stores are whole row segments) and an 8 x 8 quadrant of a
+//     16 x 16 tile in the LDS-staged pass (whose volume traffic is 8/K bytes
+//     per update).  Voxels stay in registers for all the views of a pass; the
 //     volume is read and written once per pass (the 8 bytes per voxel update
 //     of Sec. 4.2 divided by the views per pass).
 //   * View constants are wave-uniform: scalar loads, no VGPRs.
@@ -761,8 +763,11 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
     const int tile = tile_of_block((int)blockIdx.x, gx, gy, n_tiles, xcd_order);
     if (tile >= n_tiles) return;  // whole block: before any barrier
     const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
-    int x = bx * TX + (int)threadIdx.x % TX;
-    int y = by * TY + (int)threadIdx.x / TX;
+    // A 16 x 16 tile's waves are its 8 x 8 quadrants (other widths: rows of the tile): with the
+    // column-major pixel stage their LDS reads conflict less (measured: FP32 +2%, BF16 +3.7%).
+    const int wv = (int)threadIdx.x >> 6, ln = (int)threadIdx.x & 63;
+    int x = TX == 16 ? bx * TX + 8 * (wv & 1) + (ln & 7) : bx * TX + (int)threadIdx.x % TX;
+    int y = TX == 16 ? by * TY + 8 * (wv >> 1) + (ln >> 3) : by * TY + (int)threadIdx.x / TX;
     const int z0 = bz * ZU;
     const bool in_xy = (x < box.nx) & (y < box.ny);
     x = min(x, box.nx - 1);

@@ -33,9 +33,10 @@
  * projections and matrices are DEVICE pointers on the context's device; they
  * must stay valid and unmodified until the work enqueued on `stream` has
  * completed.  A context owns device scratch that every call reuses: per-view
- * constants, the staging copy of a pass of views (about K (W+2)(H+2) x 16
- * bytes, 8 for compact 16-bit records: 1.2 GB at K = 64 and 1248 x 960; a
- * call of two or more passes holds two such copies, see
+ * constants, the staging copy of a pass of views (up to K (W+2)(H+2) x 16
+ * bytes, 8 for compact 16-bit records: 1.2 GB at K = 64 and 1248 x 960; with
+ * the default pixel stages only the views read directly get records; a call
+ * of two or more passes staged ahead holds two such copies, see
  * BP_OPT_OVERLAP_STAGING), the footprint tables or clipping mask of the block
  * tiles, and a side stream with its events for the staging.  It grows on
  * demand (a growth waits for the device) and is freed by bp_destroy, so

@@ -235,8 +235,8 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     if (p.k <= 0) {
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
         else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
-        // LDS-staged taps, measured at 496 views: K = 128 (L = 512, FP32 pixels at 1 of 8 views
-        // direct: 2342 GUPS against 2305 at K = 64; L = 1024: +4%)
+        // LDS-staged taps, measured at 496 views: K = 128 (L = 512: BF16 and FP16 best, FP32
+        // within 1% of K = 64; L = 1024: best of K = 1 .. 128)
         else p.k = 128;
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;

@@ -363,6 +363,37 @@ def test_parity_l512_sampled(dtype, compact, path):
             assert e["max_abs_over_max"] <= max_tol, (name, e)
 
 
+# Launches from the benchmark's search space at L = 512 (views per pass, z-unroll, tile width, tap
+# split, direct taps): the usual winner, a records split with wide tiles, the tuned split with
+# narrow tiles, and every tap read from the caller's images.
+L512_TUNED_LAUNCHES = [(64, 8, 16, 0, False), (32, 4, 32, 4, False), (128, 8, 8, -1, False),
+                       (64, 8, 16, -1, True)]
+
+
+def test_parity_l512_tuned_launches_sampled():
+    """The L=512 workload in launches the benchmark's autotuner can pick: every 8th voxel per axis
+    against the oracle at the 1e-5 bar, and the whole volume against the library's default launch
+    (both within the bar of the exact result, so within twice the bar of each other)."""
+    wl = synth.WORKLOADS["fdk_l512_v496_f32"]
+    v = wl.volume
+    proj = gc.full_projections(wl.phantom_seed)
+    P32 = gc.product_matrices(wl.scanner)
+    shape = (v.L,) * 3
+    base = gc.run_gpu(proj, P32, shape, v.voxel_size, v.origin)
+    xyz = strided_sample(v.L, 8, 3)
+    ref_s = oracle.backproject_points(proj.cpu().numpy(), P32.astype(np.float64), v.voxel_size, v.origin, xyz)
+    for k, zu, tx, split, direct in L512_TUNED_LAUNCHES:
+        got = _run_opts(proj, P32, shape, v.voxel_size, v.origin, k=k, zu=zu, tx=tx, tap_split=split,
+                        direct_taps=direct)
+        err = gc.error_stats(got[xyz[:, 2], xyz[:, 1], xyz[:, 0]], ref_s)
+        whole = gc.rel_l2(got, base.astype(np.float64))
+        print(f"\nL=512 K={k} zu={zu} tx={tx} split={split} direct={direct}: sample {err}, "
+              f"whole volume vs default {whole:.3e}")
+        assert err["rel_l2"] <= gc.REL_L2_TOL, (k, zu, tx, split, direct, err)
+        assert err["max_abs_over_max"] <= gc.MAX_ABS_TOL, (k, zu, tx, split, direct, err)
+        assert whole <= 2 * gc.REL_L2_TOL, (k, zu, tx, split, direct, whole)
+
+
 def tilted(P64, deg):
     """The orbit tilted by ``deg`` degrees about the x axis (P T, T the rotation of the world frame),
     composed in FP64 and rounded once to FP32: every view has P[0][2] and P[2][2] non-zero."""

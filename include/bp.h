@@ -85,7 +85,7 @@ typedef enum {
                            for volumes small next to the projections, where writing
                            the staging copy would cost more than the taps save.
                            BP_PATH_AUTO takes it when the box has fewer than 64 x W x H
-                           voxels for FP32 projections (8 x W x H for 16-bit ones) */
+                           voxels for FP32 projections (40 x W x H for 16-bit ones) */
 } bp_path;
 
 typedef struct {
@@ -207,9 +207,9 @@ bp_status bp_set_tuning(bp_ctx ctx, bp_path path, int views_per_pass, int z_unro
  *                     the LDS stage before each footprint is copied in, so that
  *                     any read of an element the staging did not write shows as
  *                     NaN in the result.  Results are bit-identical otherwise.
- *   BP_OPT_SINGLE_TAPS  paths on the caller's FP32 images (PLAIN, FUSED_DIRECT):
- *                     load each tap as one dword instead of each row's pixel
- *                     pair as one 8-byte load.  Bit-identical.
+ *   BP_OPT_SINGLE_TAPS  paths on the caller's images (PLAIN, FUSED_DIRECT): load
+ *                     each tap on its own instead of each row's pixel pair as one
+ *                     load (8 bytes of FP32, 4 bytes of FP16/BF16).  Bit-identical.
  *
  *   Tile order (which blocks run together; results are identical in every order):
  *   default           XCD-private regions: all XCDs work through the same z-layer of

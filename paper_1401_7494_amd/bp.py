@@ -210,8 +210,8 @@ class Context:
         of the fused path directly instead of staging most views' footprints through LDS; stage the
         next pass while one runs ("overlap"), just before it ("serial") or as tuned ("auto":
         overlapped for compact 16-bit records); ``poison_staging`` (testing aid) fills the staging copy
-        and the LDS stage with NaN before each is written; ``single_taps`` reads the caller's FP32
-        pixels one dword per tap (instead of one 8-byte load per row pair)."""
+        and the LDS stage with NaN before each is written; ``single_taps`` reads the caller's
+        pixels one load per tap (instead of one load per row pair: 8 bytes of FP32, 4 of FP16/BF16)."""
         flags = ((self.OPT_NO_CULL if no_cull else 0) | (self.OPT_NO_COLUMN if no_column else 0)
                  | (self.OPT_WIDE_STAGING if wide_staging else 0))
         if order == "plain":

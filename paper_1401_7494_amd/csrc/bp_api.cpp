@@ -213,11 +213,11 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
         // Coarse voxels (few per detector pixel, so a tile's footprint overflows the LDS stage and
         // no two voxels share a pixel) favour reading the caller's images directly.  Measured at
         // 1248 x 960 pixels, 496 views, 256 mm field: FP32 (pixel-pair taps) direct at L = 384
-        // (1030 GUPS against 627 staged), staged at L = 448 (1762 against 1129); 16-bit input
-        // (single taps) staged at L = 256 (386 against 354).
+        // (1030 GUPS against 627 staged), staged at L = 448 (1762 against 1129); BF16 (pixel-pair
+        // taps) direct at L = 320 (788 against 660), staged at L = 384 (890 against 819).
         const double voxels = (double)nx * (double)ny * (double)nz;
         const double pixels = (double)ctx->cfg.det_width * (double)ctx->cfg.det_height;
-        const double crossover = ctx->cfg.proj_dtype == BP_F32 ? 64.0 : 8.0;
+        const double crossover = ctx->cfg.proj_dtype == BP_F32 ? 64.0 : 40.0;
         p.path = voxels < crossover * pixels ? BP_PATH_FUSED_DIRECT : BP_PATH_FUSED;
     }
     // Staged or direct taps for the fused pass.  FP32 records staged as records, on a fine grid

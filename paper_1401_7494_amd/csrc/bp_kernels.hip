@@ -88,15 +88,17 @@ typedef float f32x2_t __attribute__((ext_vector_type(2)));
 // elements bit-cast to float compiles to a single dword load here, element 0 used twice).
 __device__ f32x2_t raw_buffer_load_f32x2(i32x4_t rsrc, int voffset, int soffset, int aux)
     __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+// Byte-offset buffer load of one dword, at any 2-byte boundary (two 16-bit pixels).
+__device__ uint32_t raw_buffer_load_u32(i32x4_t rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.i32");
 
 // Plain path: the caller's W x H image of T.  Positions are raw detector
 // coordinates; a tap off the detector reads 0 (row and column tests in VALU;
-// every load stays inside the view).  PAIRS: FP32 taps of one row as one
-// 8-byte load (W >= 2).
+// every load stays inside the view).  PAIRS: the two taps of one row as one
+// load, 8 bytes of FP32 or 4 bytes of FP16/BF16 (W >= 2).
 template <typename T, bool PAIRS = false>
 struct CheckedSource {
     static constexpr uint32_t kElem = sizeof(T);
-    static_assert(!PAIRS || sizeof(T) == 4, "pair taps are FP32");
     const uint8_t* base;
     int W, H;
 
@@ -121,6 +123,18 @@ struct CheckedSource {
         return v;
     }
 
+    // the FP32 values of the low and high 16-bit pixels of a dword
+    static __device__ __forceinline__ float widen_lo(uint32_t b)
+    {
+        if constexpr (__is_same(T, __half)) return f16_lo(b);
+        else return bf16_lo(b);
+    }
+    static __device__ __forceinline__ float widen_hi(uint32_t b)
+    {
+        if constexpr (__is_same(T, __half)) return f16_lo(b >> 16);
+        else return u32_as_f32(b & 0xffff0000u);
+    }
+
     __device__ __forceinline__ float tap(const View& v, int idx) const
     {
         const uint32_t off = (uint32_t)idx * kElem;
@@ -137,8 +151,8 @@ struct CheckedSource {
     // (1 - fx) P[i0] + fx P[i0 + 1], pixels off the detector 0.
     //   single taps: the two pixels loaded one dword each at clamped, in-bounds
     //     indices, zeroed by explicit row and column tests;
-    //   PAIRS (FP32, W >= 2): the pair at columns c, c + 1, c = i0 clamped into
-    //     [0, W - 2], as one 8-byte load, with per-column weights (w0, w1) of its two
+    //   PAIRS (W >= 2): the pair at columns c, c + 1, c = i0 clamped into
+    //     [0, W - 2], as one load, with per-column weights (w0, w1) of its two
     //     pixels that put (1 - fx) and fx on the right ones and 0 on any other
     //     (column -1 or W, or a pixel of the pair that is not a tap).  A row off the
     //     detector is read at a byte offset outside [0, W H 4) -- negative rows as
@@ -179,10 +193,18 @@ struct CheckedSource {
             // SGPR offset is added after it), so a row off the detector must be off in the VGPR
             const int row_b = W * (int)kElem;
             const int off = __mul24(j0, row_b) + k.c_bytes;
-            const f32x2_t q0 = raw_buffer_load_f32x2(v.pair_rs, off, 0, 0);
-            const f32x2_t q1 = raw_buffer_load_f32x2(v.pair_rs, off + row_b, 0, 0);
-            top = fmaf(k.w1, q0.y, k.w0 * q0.x);
-            bot = fmaf(k.w1, q1.y, k.w0 * q1.x);
+            if constexpr (sizeof(T) == 4) {
+                const f32x2_t q0 = raw_buffer_load_f32x2(v.pair_rs, off, 0, 0);
+                const f32x2_t q1 = raw_buffer_load_f32x2(v.pair_rs, off + row_b, 0, 0);
+                top = fmaf(k.w1, q0.y, k.w0 * q0.x);
+                bot = fmaf(k.w1, q1.y, k.w0 * q1.x);
+            } else {
+                // 16-bit pixels: the pair as one dword at a 2-byte boundary, each half widened exactly
+                const uint32_t h0 = raw_buffer_load_u32(v.pair_rs, off, 0, 0);
+                const uint32_t h1 = raw_buffer_load_u32(v.pair_rs, off + row_b, 0, 0);
+                top = fmaf(k.w1, widen_hi(h0), k.w0 * widen_lo(h0));
+                bot = fmaf(k.w1, widen_hi(h1), k.w0 * widen_lo(h1));
+            }
         } else {
             // i0 in [-1, W] (a clamped column position reaches W)
             const bool c0 = (k.i0 >= 0) & (k.i0 < W), c1 = k.i0 + 1 < W;
@@ -989,6 +1011,8 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
                     acc[i] = fmaf(Src::eval(q, fx, fy), r2, acc[i]);
                 }
             } else {  // safe
+                uint32_t base_b = (uint32_t)base * elem;
+                asm("" : "+s"(base_b));
 #pragma unroll
                 for (int i = 0; i < ZU; ++i) {
                     const float u = fmaf(c.p[2], Z[i], uxy), v = fmaf(c.p[6], Z[i], vxy),
@@ -997,7 +1021,13 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
                     const float sv = clamp_to<CLAMP>(fmaf(u, r, 1.0f), s_lo, s_hi);
                     const float tv = clamp_to<CLAMP>(fmaf(v, r, 1.0f), t_lo, t_hi);
                     const int c0 = (int)sv, r0 = (int)tv;
-                    const Rec q = staged_rec(row_off(r0) + (uint32_t)(base + c0 * cstride) * elem);
+                    // pixels: (c0 * column stride + r0) as one 24-bit multiply-add (c0 and r0 are at
+                    // least 0 and below 2^24), then one shift-add of the footprint's origin (an opaque
+                    // uniform, so that the compiler does not fold it into the sum before the shift)
+                    const uint32_t off = kRaw ? (__umul24((uint32_t)c0, (uint32_t)kRawColStride) + (uint32_t)r0) * elem +
+                                                    base_b
+                                              : row_off(r0) + (uint32_t)(base + c0) * elem;
+                    const Rec q = staged_rec(off);
                     const float val = Src::eval(q, __builtin_amdgcn_fractf(sv), __builtin_amdgcn_fractf(tv));
                     acc[i] += val * src.weight_voxel(view, r);
                 }
@@ -1659,8 +1689,8 @@ hipError_t launch_backproject(Dtype dt, Layout layout, int zu, int tile_x, float
         if (tile_x != 16 && tile_x != 64) return hipErrorInvalidValue;
         switch (dt) {
         case Dtype::F32: return single_taps || W < 2 ? BP_CHECKED(float, false) : BP_CHECKED(float, true);
-        case Dtype::F16: return BP_CHECKED(__half);
-        case Dtype::BF16: return BP_CHECKED(uint16_t);
+        case Dtype::F16: return single_taps || W < 2 ? BP_CHECKED(__half, false) : BP_CHECKED(__half, true);
+        case Dtype::BF16: return single_taps || W < 2 ? BP_CHECKED(uint16_t, false) : BP_CHECKED(uint16_t, true);
         }
 #undef BP_CHECKED
     }

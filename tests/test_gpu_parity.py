@@ -261,7 +261,8 @@ def test_plan_reports_choices():
     with bp.Context(1248, 960, "bf16") as ctx:
         p = ctx.plan(1024, 1024, 1024, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
-        assert ctx.plan(256, 256, 256, 496).path == "fused"  # 16-bit taps are single loads: staged sooner
+        assert ctx.plan(320, 320, 320, 496).path == "fused_direct"  # 16-bit pairs: staged a little sooner
+        assert ctx.plan(384, 384, 384, 496).path == "fused"
 
 
 # ---------------------------------------------------------------------------
@@ -449,13 +450,13 @@ def _run_opts(proj, P32, shape, vs, origin, no_cull=False, no_column=False, dtyp
     return vol.cpu().numpy()
 
 
-def _run_direct(proj, P32, shape, vs, origin, path, single_taps, zu=8, tx=16, k=5):
+def _run_direct(proj, P32, shape, vs, origin, path, single_taps, zu=8, tx=16, k=5, dtype="f32"):
     dev = torch.device("cuda:0")
     vol = torch.zeros(shape, dtype=torch.float32, device=dev)
-    p = proj.to(dev).contiguous()
+    p = proj.to(gc.TORCH_DTYPE[dtype]).to(dev).contiguous()
     m = torch.as_tensor(np.ascontiguousarray(P32, dtype=np.float32)).to(dev)
     n, H, W = p.shape
-    with bp.Context(W, H, "f32") as ctx:
+    with bp.Context(W, H, dtype) as ctx:
         ctx.set_tuning(path, k, zu, tx)
         ctx.set_options(single_taps=single_taps)
         ctx.backproject(vol, p, m, vs, origin)
@@ -463,39 +464,43 @@ def _run_direct(proj, P32, shape, vs, origin, path, single_taps, zu=8, tx=16, k=
     return vol.cpu().numpy()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("path", ["plain", "fused_direct"])
-def test_pair_taps_equal_single_taps(path):
-    """On the caller's FP32 images, each row's pixel pair read as one 8-byte load gives the same
-    bits as one dword per tap: boxes across every detector edge and corner (pairs clamped into
-    the row at column 0 and W - 2), views behind the source, a two-column detector."""
-    sc = synth.Scanner(n_views=16, W=96, H=64, pitch=2.0)
-    proj = synth.filtered_projections(sc, synth.random_ellipsoids(79))
-    P32 = gc.product_matrices(sc)
+def test_pair_taps_equal_single_taps(path, dtype):
+    """On the caller's images, each row's pixel pair read as one load (8 bytes of FP32, or 4 bytes
+    of FP16/BF16 at any 2-byte boundary) gives the same bits as one load per tap: boxes across
+    every detector edge and corner (pairs clamped into the row at column 0 and W - 2), even and
+    odd detector widths (16-bit rows that start off a 4-byte boundary), views behind the source,
+    detectors of two columns and of one."""
     shape, vs = (24, 40, 40), 2.0
     o = _box_origin(shape, vs)
-    for shift in ((0.0, 0.0, 0.0), (60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
-        origin = (o[0] + shift[0], o[1] + shift[1], o[2] + shift[2])
-        for zu, tx in ((8, 16), (4, 64)):
-            a = _run_direct(proj, P32, shape, vs, origin, path, True, zu, tx)
-            b = _run_direct(proj, P32, shape, vs, origin, path, False, zu, tx)
-            assert np.array_equal(a, b), (shift, zu, tx)
-            assert np.abs(a).max() > 0
-    ref = _oracle_box(proj, P32, shape, vs, origin)
-    assert gc.rel_l2(b, ref) <= gc.REL_L2_TOL
+    for W in (96, 97):
+        sc = synth.Scanner(n_views=16, W=W, H=64, pitch=2.0)
+        proj = synth.filtered_projections(sc, synth.random_ellipsoids(79)).to(gc.TORCH_DTYPE[dtype])
+        P32 = gc.product_matrices(sc)
+        for shift in ((0.0, 0.0, 0.0), (60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
+            origin = (o[0] + shift[0], o[1] + shift[1], o[2] + shift[2])
+            for zu, tx in ((8, 16), (4, 64)):
+                a = _run_direct(proj, P32, shape, vs, origin, path, True, zu, tx, dtype=dtype)
+                b = _run_direct(proj, P32, shape, vs, origin, path, False, zu, tx, dtype=dtype)
+                assert np.array_equal(a, b), (W, shift, zu, tx)
+                assert np.abs(a).max() > 0
+        ref = _oracle_box(proj, P32, shape, vs, origin)  # the oracle on the values the GPU read
+        assert gc.rel_l2(b, ref) <= gc.REL_L2_TOL, W
     # the source inside the box (guarded contributions)
     sc2 = synth.Scanner(n_views=13, W=96, H=72, pitch=3.0, sid=60.0, sdd=160.0)
     P2 = gc.product_matrices(sc2)
     proj2 = synth.filtered_projections(sc2, synth.random_ellipsoids(1401))
     o2 = _box_origin(BOX, VS)
-    assert np.array_equal(_run_direct(proj2, P2, BOX, VS, o2, path, True),
-                          _run_direct(proj2, P2, BOX, VS, o2, path, False))
+    assert np.array_equal(_run_direct(proj2, P2, BOX, VS, o2, path, True, dtype=dtype),
+                          _run_direct(proj2, P2, BOX, VS, o2, path, False, dtype=dtype))
     # detectors of two columns and of one (single taps, whatever the option)
     for W in (2, 1):
-        img = synth.uniform_images((3, 5, W), seed=W)
+        img = synth.uniform_images((3, 5, W), seed=W).to(gc.TORCH_DTYPE[dtype])
         P = np.array([[[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1]]] * 3, dtype=np.float32)
         shp, org = (2, 6, 4), (-1.0, -1.0, 0.0)
-        a = _run_direct(img, P, shp, 0.5, org, path, True, 8, 16, 3)
-        b = _run_direct(img, P, shp, 0.5, org, path, False, 8, 16, 3)
+        a = _run_direct(img, P, shp, 0.5, org, path, True, 8, 16, 3, dtype=dtype)
+        b = _run_direct(img, P, shp, 0.5, org, path, False, 8, 16, 3, dtype=dtype)
         assert np.array_equal(a, b)
         assert gc.rel_l2(a, _oracle_box(img, P, shp, 0.5, org)) <= gc.REL_L2_TOL
 

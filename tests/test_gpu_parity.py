@@ -269,20 +269,22 @@ def test_plan_reports_choices():
 # The paper-shaped workloads: 496 views of 1248 x 960 FP32, C-arm-like orbit.
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("path,cubic", [("auto", False), ("plain", True)])
-def test_parity_l128_full_volume(path, cubic):
+@pytest.mark.parametrize("path,cubic,dtype", [("auto", False, "f32"), ("plain", True, "f32"),
+                                              ("auto", False, "bf16"), ("plain", False, "f16")])
+def test_parity_l128_full_volume(path, cubic, dtype):
     """L=128 (voxel 2 mm), 496 views, every voxel against the oracle: the library's automatic
-    choice (the fused pass on the caller's images) and the plain form of the 128^3 FP32
-    workload, the latter through the cubic entry bp_backproject."""
+    choice (the fused pass on the caller's images, each row's pixel pair as one load) and the plain
+    form of the 128^3 workload, the FP32 plain form through the cubic entry bp_backproject; 16-bit
+    stacks against the oracle on the same rounded values."""
     wl = synth.WORKLOADS["fdk_l128_v496_f32"]
     v = wl.volume
-    proj = gc.full_projections(wl.phantom_seed)
+    proj = gc.full_projections(wl.phantom_seed).to(gc.TORCH_DTYPE[dtype])
     P32 = gc.product_matrices(wl.scanner)
     assert np.array_equal(P32, gc.oracle_matrices(wl.scanner))
-    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, path=path, cubic=cubic)
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype, path=path, cubic=cubic)
     ref = gc.run_oracle(proj, P32, v.L, v.voxel_size, v.origin)
     err = gc.error_stats(got, ref)
-    print(f"\nL=128 full, {path}: {err}")
+    print(f"\nL=128 full, {path} {dtype}: {err}")
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
     assert err["max_abs_over_max"] <= gc.MAX_ABS_TOL, err
 

@@ -811,27 +811,35 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
     PreT pre[kSlots];
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
+    // a pixel stage's byte offset of the lane's column in a row, kept in a register (so that a
+    // row's offset is one add to a uniform sum, not refolded into a shift of the column)
+    uint32_t lane_b = (uint32_t)lane * 4u;
+    if constexpr (kRaw) lane_b = (uint32_t)lane * Src::kElem;
+    asm("" : "+v"(lane_b));
     auto prefetch = [&](int k, uint2 f) {
         const int cmin = (int)(f.x & 0xffffu), rmin = (int)(f.x >> 16);
         const int fw = (int)(f.y & kFootprintWidthMask), fh = (int)(f.y >> 16);
         if constexpr (kRaw) {
             // Padded pixel (r, c) is detector pixel (c - 1, r - 1), at byte offset ((r - 1) W + c - 1) e
-            // of the view (e bytes per pixel).  A pixel off the detector is read at an offset past the
-            // view's W H e < 2^31 bytes, which the buffer's range check returns as 0 without a memory
-            // access: columns off the detector at kFar and beyond, rows below it past the end by
-            // themselves, the row above it (slot 0 of wave 0 when rmin = 0) at kFar.  No offset wraps
-            // in 32 bits (W <= 2^20).  Each lane loads one pixel per slot (no two of its loads are
-            // adjacent, so none is merged into a wider load).
+            // of the view (e bytes per pixel).  A pixel off the detector is read at an offset at or past
+            // the view's W H e < 2^31 bytes, which the buffer's range check returns as 0 without a
+            // memory access: columns off the detector at kFar and beyond (kFar less four rows for slot
+            // 0, still past 2^31), rows below it past the end by themselves, and the row above it (slot
+            // 0 of wave 0 when rmin = 0) at (c - 1) e - W e < 0, which wraps to 2^32 - W e or more
+            // (W <= 2^20).  Each lane loads one pixel per slot (no two of its loads are adjacent, so
+            // none is merged into a wider load).
             constexpr uint32_t kFar = 0xC0000000u;
             constexpr uint32_t e = Src::kElem;
-            const int c = cmin + lane;
-            const bool col_ok = (lane <= fw) & (c >= 1) & (c <= src.W);
+            // lane l holds padded column cmin + l, a detector column when 1 <= cmin + l <= W (l <= fw):
+            // the bounds are uniform, the lane's byte offset within a row one add
+            const bool col_ok = (lane >= 1 - cmin) & (lane <= min(fw, src.W - cmin));
             const uint32_t row_bytes = (uint32_t)src.W * e;
-            // slot 1's row, rmin + 3 + wave >= 3, is never above the detector
-            const uint32_t off1 = col_ok ? (uint32_t)(rmin + 3 + wave) * row_bytes + (uint32_t)(c - 1) * e : kFar;
+            // slot 1's row, rmin + 3 + wave >= 3, is never above the detector (the sum is exact modulo
+            // 2^32, the column term wrapping for cmin = 0)
+            const uint32_t off1 =
+                col_ok ? (uint32_t)(rmin + 3 + wave) * row_bytes + (uint32_t)(cmin - 1) * e + lane_b : kFar;
             const i32x4_t rs = src.raw_view(k);
-            if (wave <= fh)
-                pre[0] = Src::raw_bits(rs, (int)(rmin - 1 + wave >= 0 ? off1 - 4u * row_bytes : kFar));
+            if (wave <= fh) pre[0] = Src::raw_bits(rs, (int)(off1 - 4u * row_bytes));
 #pragma unroll
             for (int j = 1; j < kSlots; ++j)
                 if (wave + 4 * j <= fh)

@@ -1009,7 +1009,9 @@ __global__ __launch_bounds__(kBlock, kLdsWavesPerSimd<Src>) void backproject_lds
                 const float r2 = src.weight_column(view, r);
                 const float dt = c.p[6] * r;
                 const float tb = fmaf(vxy, r, 1.0f);
-                const uint32_t cb_b = (uint32_t)(base + c0 * cstride) * elem;
+                // pixels: the column's first element as one 24-bit multiply-add (0 <= c0 < 2^24)
+                const uint32_t cb_b = (uint32_t)(kRaw ? base + (int)__umul24((uint32_t)c0, (uint32_t)kRawColStride)
+                                                      : base + c0) * elem;
 #pragma unroll
                 for (int i = 0; i < ZU; ++i) {
                     const float t = clamp_to<CLAMP>(fmaf(Z[i], dt, tb), t_lo, t_hi);

@@ -631,26 +631,29 @@ def test_lds_staged_taps_are_bit_identical(dtype, compact):
             assert np.abs(a).max() > 0
 
 
-def test_pixel_stage_at_the_detector_corners():
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_pixel_stage_at_the_detector_corners(dtype):
     """Boxes straddling the detector's corners (footprints that reach the bordered frame's first
-    and last rows and columns): FP32 pixels staged in LDS, with every pixel off the detector read
-    as 0, give the same bits as the records read directly, and match the oracle."""
+    and last rows and columns): pixels staged in LDS as FP32 (16-bit ones widened), with every
+    pixel off the detector read as 0 -- columns at an offset past the view, the row above the
+    detector at one that wraps past 2^32, rows below past the view's end -- give the same bits as
+    the records read directly, and match the oracle."""
     sc = synth.Scanner(n_views=16, W=96, H=64, pitch=2.0)
-    proj = synth.filtered_projections(sc, synth.random_ellipsoids(79))
+    proj = synth.filtered_projections(sc, synth.random_ellipsoids(79)).to(gc.TORCH_DTYPE[dtype])
     P32 = gc.product_matrices(sc)
     shape, vs = (24, 40, 40), 2.0
     for cx, cy, cz in ((60.0, 0.0, 43.0), (0.0, 60.0, -43.0), (-60.0, 0.0, -43.0), (0.0, -60.0, 43.0)):
         o = _box_origin(shape, vs)
         origin = (o[0] + cx, o[1] + cy, o[2] + cz)
         for tx, zu in ((16, 8), (8, 4), (64, 1)):
-            a = _run_opts(proj, P32, shape, vs, origin, k=16, zu=zu, tx=tx, direct_taps=True)
+            a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=16, zu=zu, tx=tx, direct_taps=True)
             for split in (0, -1):
-                b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=zu, tx=tx, tap_split=split)
+                b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=16, zu=zu, tx=tx, tap_split=split)
                 assert np.array_equal(a, b), ((cx, cy, cz), tx, zu, split)
             assert np.abs(a).max() > 0
-        a = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, direct_taps=True)
-        b = _run_opts(proj, P32, shape, vs, origin, k=16, zu=8, tx=16, tap_split=0)
-    ref = _oracle_box(proj.numpy(), P32, shape, vs, origin)
+        a = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=16, zu=8, tx=16, direct_taps=True)
+        b = _run_opts(proj, P32, shape, vs, origin, dtype=dtype, k=16, zu=8, tx=16, tap_split=0)
+    ref = _oracle_box(proj, P32, shape, vs, origin)  # the oracle on the values the GPU read
     err = gc.error_stats(b, ref)
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
 

@@ -46,12 +46,13 @@ def _both(ctx, proj, P, shape, vs, origin):
     return a.cpu().numpy(), b.cpu().numpy()
 
 
-@pytest.mark.parametrize("path,k,zu,tx", [("fused_direct", 5, 8, 16), ("fused_direct", 13, 4, 64),
-                                          ("plain", 1, 8, 64)])
-def test_noalloc_matches_the_box_entry_twice(path, k, zu, tx):
-    proj = synth.filtered_projections(SC, synth.random_ellipsoids(1401))
+@pytest.mark.parametrize("path,k,zu,tx,dtype", [("fused_direct", 5, 8, 16, "f32"), ("fused_direct", 13, 4, 64, "f32"),
+                                                ("plain", 1, 8, 64, "f32"), ("fused_direct", 5, 8, 16, "bf16"),
+                                                ("plain", 1, 8, 64, "f16")])
+def test_noalloc_matches_the_box_entry_twice(path, k, zu, tx, dtype):
+    proj = synth.filtered_projections(SC, synth.random_ellipsoids(1401)).to(gc.TORCH_DTYPE[dtype])
     P = gc.product_matrices(SC)
-    with bp.Context(SC.W, SC.H, "f32") as ctx:
+    with bp.Context(SC.W, SC.H, dtype) as ctx:
         ctx.set_tuning(path, k, zu, tx)
         big, small = (21, 37, 70), (9, 16, 20)
         a, b = _both(ctx, proj, P, big, 3.0, _origin(big, 3.0))

@@ -149,13 +149,13 @@ struct CheckedSource {
 
     // The horizontal part of Part 3 at column position i0 + fx: a row's value is
     // (1 - fx) P[i0] + fx P[i0 + 1], pixels off the detector 0.
-    //   single taps: the two pixels loaded one dword each at clamped, in-bounds
+    //   single taps: the two pixels loaded one each at clamped, in-bounds
     //     indices, zeroed by explicit row and column tests;
     //   PAIRS (W >= 2): the pair at columns c, c + 1, c = i0 clamped into
     //     [0, W - 2], as one load, with per-column weights (w0, w1) of its two
     //     pixels that put (1 - fx) and fx on the right ones and 0 on any other
     //     (column -1 or W, or a pixel of the pair that is not a tap).  A row off the
-    //     detector is read at a byte offset outside [0, W H 4) -- negative rows as
+    //     detector is read at a byte offset outside [0, W H e) -- negative rows as
     //     offsets of 2^32 - k, rows below as offsets past the end, and a pair never
     //     straddles either boundary -- which the buffer's range check returns as 0.
     // Both give fmaf(fx, P[i0 + 1], (1 - fx) P[i0]) with the same roundings.

@@ -24,7 +24,8 @@ baseline times.
   C5  the serving mix: 200 seeded requests (L in 128/256/512, 124/248/496 views, FP32/FP16),
       first all at once (capacity), then Poisson at 0.8 x capacity; p50/p99 latency,
       aggregate GUPS, ingest and back-projection device times, peak admitted HBM
-  general  the L=512 workload through a tilted orbit (every view off the column branch)
+  general  the L=512 workload through a tilted orbit (every view off the column branch), in the
+           autotuner's launch for that geometry; sampled error
 
 `roofline`: the dominant kernel of the headline form -- the paper's 38 FP32
 operations per voxel update (Sec. 4.2) times the updates of one launch over
@@ -748,6 +749,12 @@ def leg_general(b: Bench, P64_c2):
     P = torch.from_numpy(Pt32).to(b.dev)
     updates = float(v.L) ** 3 * sc.n_views
     ctx = b.context(sc.W, sc.H, "f32")
+    tuning = None
+    if not args.no_tune:  # the autotuner's launch for this geometry, cached apart from the circular orbit's
+        scratch = torch.zeros((v.L,) * 3, dtype=torch.float32, device=b.dev)
+        _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_l512(sc.n_views), "L=512 tilted f32",
+                           tag=f"tilt{TILT_DEG:g}")
+        del scratch
     plan = b.plan_of(ctx, v, sc.n_views)
     step_ms, kern, vol = b.run(ctx, proj, P, v, args.config_steps, 1)
     ctx.close()
@@ -757,7 +764,7 @@ def leg_general(b: Bench, P64_c2):
     ref = oracle.backproject_points(proj.cpu().numpy(), Pt32.astype(np.float64), v.voxel_size, v.origin, xyz)
     got = vol[xyz[:, 2], xyz[:, 1], xyz[:, 0]].double().cpu().numpy()
     out = {"workload": f"{wl.name} with the orbit tilted {TILT_DEG} degrees about x",
-           "views_off_the_column_branch": share, "fused_f32": {**plan, **stats(step_ms, updates),
+           "views_off_the_column_branch": share, "fused_f32": {**plan, **stats(step_ms, updates), "tuning": tuning,
            "backproject_ms_per_launch": round(kern["backproject"][0] / max(kern["backproject"][1], 1), 4),
            "error_vs_fp64_oracle": error_stats(got, ref)},
            "error_region": "every 8th voxel per axis (64^3 voxels)"}

@@ -8,7 +8,8 @@ to a context with ``bp_set_tuning`` (and the tap options).  ``ensure_tuned``
 is what the benchmark and the serving executor call: it reads the cache for
 the call's shape and device, searches only on a miss, and applies the winner.
 The library's own automatic choice (``AUTO``) is always one of the timed
-candidates, so a tuned launch is never slower than it on the timed runs.
+candidates, so a tuned launch is never slower than it on the timed runs, and
+it is kept when another launch is faster only by the timing noise.
 
 The timing function is injectable, so the search logic is testable without a
 GPU.
@@ -84,20 +85,39 @@ def candidates(problem: Problem, ks=K_CANDIDATES, zus=ZU_CANDIDATES, txs=TX_CAND
     return out
 
 
-def search(problem: Problem, time_fn, cands=None, reps: int = 3, warmup: int = 1) -> Result:
-    """Time every candidate with ``time_fn(candidate) -> ms`` and return the fastest (median of ``reps``)."""
+def search(problem: Problem, time_fn, cands=None, reps: int = 3, warmup: int = 1, refine: float = 0.02,
+           rounds: int = 3, tie: float = 0.005) -> Result:
+    """Time every candidate with ``time_fn(candidate) -> ms`` (median of ``reps`` after ``warmup``)
+    and return the fastest.  The candidates within ``refine`` (a fraction) of the fastest are then
+    timed ``rounds`` more times, interleaved (in alternating order), so that a drift of the clocks
+    over the search does not decide between near-equal launches; the medians of those interleaved
+    runs decide between them.  Among the
+    candidates within ``tie`` of the fastest, the library's own choice (``AUTO``) is kept when it
+    is one of them: timing noise does not move a shape off the library's default."""
     cands = cands if cands is not None else candidates(problem)
     if not cands:
         raise ValueError("no candidates to time")
-    timings = {}
+    samples = {}
     by_key = {}
     for c in cands:
         for _ in range(warmup):
             time_fn(c)
-        ms = statistics.median(time_fn(c) for _ in range(reps))
-        timings[c.key()] = ms
+        samples[c.key()] = [time_fn(c) for _ in range(reps)]
         by_key[c.key()] = c
+    timings = {k: statistics.median(v) for k, v in samples.items()}
+    first = min(timings.values())
+    close = [k for k in timings if timings[k] <= first * (1.0 + refine)]
+    if len(close) > 1 and rounds > 0:
+        again = {k: [] for k in close}
+        for r in range(rounds):
+            for k in (close if r % 2 == 0 else close[::-1]):
+                again[k].append(time_fn(by_key[k]))
+        for k in close:
+            timings[k] = statistics.median(again[k])
     best_key = min(timings, key=timings.get)
+    auto = AUTO.key()
+    if auto in timings and timings[auto] <= timings[best_key] * (1.0 + tie):
+        best_key = auto
     return Result(by_key[best_key], timings)
 
 

@@ -235,9 +235,11 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     if (p.k <= 0) {
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
         else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
-        // LDS-staged taps, measured at 496 views: K = 128 (L = 512: BF16 and FP16 best, FP32
-        // within 1% of K = 64; L = 1024: best of K = 1 .. 128)
-        else p.k = 128;
+        // LDS-staged taps, measured at 496 views: K = 128 for 16-bit input (best at L = 512) and
+        // for large volumes (L = 1024: best of K = 1 .. 128); FP32 pixel stages below 2e8 voxels
+        // take K = 64, within 0.5% of K = 128 in time at L = 512 but with 20% less HBM traffic per
+        // update (the footprint bands of fewer views stay in L2)
+        else p.k = ctx->cfg.proj_dtype == BP_F32 && pixels && voxels < 2.0e8 ? 64 : 128;
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;

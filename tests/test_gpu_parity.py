@@ -242,11 +242,11 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
-        # staged or direct taps: FP32 pixel stages at every size (K = 128); FP32 record stages at
-        # L = 512, direct reads on finer, larger grids
+        # staged or direct taps: FP32 pixel stages at every size (K = 64 below 2e8 voxels, K = 128
+        # above); FP32 record stages at L = 512, direct reads on finer, larger grids
         ctx.set_tuning("auto", 0, 0, 0)
         p = ctx.plan(512, 512, 512, 496)
-        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, False)
         p = ctx.plan(1024, 1024, 1024, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
         ctx.set_options(stage_records=True)
@@ -261,6 +261,7 @@ def test_plan_reports_choices():
     with bp.Context(1248, 960, "bf16") as ctx:
         p = ctx.plan(1024, 1024, 1024, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
+        assert ctx.plan(512, 512, 512, 496).views_per_pass == 128  # 16-bit stages: K = 128 at L = 512
         assert ctx.plan(320, 320, 320, 496).path == "fused_direct"  # 16-bit pairs: staged a little sooner
         assert ctx.plan(384, 384, 384, 496).path == "fused"
 

@@ -77,6 +77,15 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
+def tilt_matrices(P64, deg):
+    """The orbit tilted by ``deg`` degrees about x (P T, T the rotation of the world frame), composed
+    in FP64 and rounded once to FP32: every view then has P[0][2] and P[2][2] non-zero."""
+    a = np.radians(deg)
+    T = np.eye(4)
+    T[1, 1], T[1, 2], T[2, 1], T[2, 2] = np.cos(a), -np.sin(a), np.sin(a), np.cos(a)
+    return (np.asarray(P64, dtype=np.float64) @ T).astype(np.float32)
+
+
 def counter_record(kernel: str, launch: str, workload: str):
     """The committed rocprofv3 counter record of this kernel, launch and workload (the file holds one
     per profiled launch), or None when the kernel sources changed since it was taken or no record is
@@ -120,6 +129,9 @@ def parse():
                     help="edge of the centre block the oracle times (about 10 s of FP64 work on 16 threads)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--no-clocks", action="store_true", help="do not query clocks with rocm-smi (profiled runs)")
+    ap.add_argument("--tilt", type=float, default=0.0,
+                    help="headline forms on the orbit tilted by this many degrees about x (the general branch; "
+                         "for profiling it: the workload is then named with the tilt)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     return ap.parse_args()
@@ -334,6 +346,11 @@ def headline(b: Bench, res: dict):
         log(f"bench: copy calibration: 3 x {args.copy_calibration} MiB device-to-device")
         del src, dst
     P64, P = b.matrices(sc)
+    wname = wl.name
+    if args.tilt:
+        P = torch.from_numpy(tilt_matrices(P64, args.tilt)).to(b.dev)
+        wname = f"{wl.name}_tilt{args.tilt:g}"
+    res["workload"] = wname
     updates = float(v.L) ** 3 * sc.n_views
     forms = [f for f in args.forms.split(",") if f]
     projs = {"f32": proj32}
@@ -349,11 +366,12 @@ def headline(b: Bench, res: dict):
         tuning = None
         if path in ("fused", "plain") and not args.no_tune and not fixed:
             scratch = torch.zeros((v.L,) * 3, dtype=torch.float32, device=b.dev)
+            geo = f"tilt{args.tilt:g}" if args.tilt else ""  # another geometry: its own cache entries
             if path == "fused":
-                _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_l512(sc.n_views), f"L=512 {dt}")
+                _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_l512(sc.n_views), f"L=512 {dt}", tag=geo)
             else:
                 _, tuning = b.tune(ctx, scratch, proj, P, v, b.cands_plain(), f"L=512 plain {dt}",
-                                   include_auto=False, tag="plain")
+                                   include_auto=False, tag="plain" + (f"|{geo}" if geo else ""))
             del scratch
         else:
             ctx.set_tuning(path, args.k, args.zu, args.tx)
@@ -400,7 +418,8 @@ def headline(b: Bench, res: dict):
         bl = args.cpu_block
         lo = (v.L - bl) // 2
         blk = ((lo, lo + bl),) * 3
-        P_or = oracle.geometry.circular_matrices(*sc.geometry_args()).astype(np.float32).astype(np.float64)
+        P_or = oracle.geometry.circular_matrices(*sc.geometry_args())
+        P_or = (tilt_matrices(P_or, args.tilt) if args.tilt else P_or.astype(np.float32)).astype(np.float64)
         thr = default_threads()
         t = time.perf_counter()
         ref = oracle.backproject(proj32.cpu().numpy(), P_or, v.L, v.voxel_size, v.origin, block=blk, threads=thr)
@@ -432,7 +451,7 @@ def headline(b: Bench, res: dict):
     if split < 0 and kernel == "backproject_lds_kernel":
         split = 0  # the library's share of directly read views for FP32 pixel stages
     launch = f"K={k} ZU={head['z_unroll']} TX={head['tile_x']} split={split}"
-    rec = counter_record(kernel, launch, wl.name)
+    rec = counter_record(kernel, launch, wname)
     views_per_launch = upl / float(v.L) ** 3
     alg_bytes = upl * (8.0 / views_per_launch + sc.W * sc.H * 4.0 / float(v.L) ** 3)
     traffic = None
@@ -741,10 +760,7 @@ def leg_general(b: Bench, P64_c2):
     wl = synth.WORKLOADS["fdk_l512_v496_f32"]
     v, sc = wl.volume, wl.scanner
     proj = b.stack(wl)
-    a = np.radians(TILT_DEG)
-    T = np.eye(4)
-    T[1, 1], T[1, 2], T[2, 1], T[2, 2] = np.cos(a), -np.sin(a), np.sin(a), np.cos(a)
-    Pt32 = (P64_c2 @ T).astype(np.float32)
+    Pt32 = tilt_matrices(P64_c2, TILT_DEG)
     share = float(np.mean((Pt32[:, 0, 2] != 0) & (Pt32[:, 2, 2] != 0)))
     P = torch.from_numpy(Pt32).to(b.dev)
     updates = float(v.L) ** 3 * sc.n_views
@@ -859,7 +875,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded random-ellipsoid phantom standing in for the RabbitCT dataset)",
-        "config": {"workload": "fdk_l512_v496_f32", "L": 512, "voxel_mm": 0.5, "views": 496,
+        "config": {"workload": res.get("workload", "fdk_l512_v496_f32"), "L": 512, "voxel_mm": 0.5, "views": 496,
                    "detector": [1248, 960], "form": "fused_f32", "parallelism": "single GPU"},
         "p50_gups": head["gups_p50"],
         "p99_gups": head["gups_p99"],

@@ -28,8 +28,8 @@ def test_search_picks_the_fastest_by_median():
     r = at.search(P, fake, reps=3, warmup=1)
     assert r.best == at.Candidate("fused", 64, 8, 16)  # the staged (tuned split) candidate comes first
     best = r.timings_ms[r.best.key()]
-    for c, n in calls.items():  # 1 warm-up + 3 timed; the candidates within 2% of the best 3 more
-        assert n == (7 if r.timings_ms[c.key()] <= best * 1.02 else 4), (c, n)
+    for c, n in calls.items():  # 1 warm-up + 3 timed; the candidates within 2% of the best 7 more
+        assert n == (11 if r.timings_ms[c.key()] <= best * 1.02 else 4), (c, n)
     assert len(r.timings_ms) == len(at.candidates(P))
 
 
@@ -54,9 +54,9 @@ def test_search_retimes_near_equal_launches_interleaved():
 def test_search_keeps_the_library_choice_within_the_noise():
     auto, fast = at.AUTO, at.Candidate("fused", 64, 8, 16, 0)
     r = at.search(P, lambda c: 10.0 if c == auto else 9.97, cands=[auto, fast], reps=1, warmup=0)
-    assert r.best == auto  # 0.3% faster is within the 0.5% tie
-    r = at.search(P, lambda c: 10.0 if c == auto else 9.9, cands=[auto, fast], reps=1, warmup=0)
-    assert r.best == fast  # 1% is not
+    assert r.best == auto  # 0.3% faster is within the 1% tie
+    r = at.search(P, lambda c: 10.0 if c == auto else 9.85, cands=[auto, fast], reps=1, warmup=0)
+    assert r.best == fast  # 1.5% is not
     r = at.search(P, lambda c: 10.0 if c == auto else 9.97, cands=[auto, fast], reps=1, warmup=0, tie=0.0)
     assert r.best == fast
 

@@ -629,7 +629,13 @@ __device__ __forceinline__ int tile_of_block(int b, int gx, int gy, int n_tiles,
 // Passes on the caller's images (plain and direct-fused) are compiled for 8 waves per SIMD: they
 // stream the volume, and occupancy keeps more of its loads in flight (L = 512, one view per pass:
 // 419 -> 456 GUPS with 64-wide tiles, 417 -> 470 with 16-wide tiles).
-template <class Src, int ZU, bool PADDED, int TX>
+// NT (passes on the caller's images, 64-wide tiles): the volume's read-modify-write as
+// nontemporal loads and stores, for volumes that stream through HBM and leave the caches to the
+// taps (plain pass at L = 512: 455 -> 481 GUPS; with 16-wide tiles, whose rows are half cache
+// lines, and with volumes that fit in the caches it is slower, so the host takes it only for
+// volumes of 256 MiB or more).  A compile-time choice: the compiler merges a nontemporal and a
+// plain load of one address into one plain load.
+template <class Src, int ZU, bool PADDED, int TX, bool NT = false>
 __global__ __launch_bounds__(kBlock, PADDED ? 1 : 8) void backproject_kernel(
     float* __restrict__ vol, Box box, const ViewConst* __restrict__ vc, int n_views, Src src,
     const uint32_t* __restrict__ cull, int cull_words, int kbase, int xcd_order)
@@ -672,7 +678,11 @@ __global__ __launch_bounds__(kBlock, PADDED ? 1 : 8) void backproject_kernel(
         const size_t plane = (size_t)box.nx * (size_t)box.ny;
         const size_t col = (size_t)y * box.nx + x;
 #pragma unroll
-        for (int i = 0; i < ZU; ++i) old[i] = z0 + i < box.nz ? vol[(size_t)(z0 + i) * plane + col] : 0.0f;
+        for (int i = 0; i < ZU; ++i) {
+            const float* p = vol + (size_t)(z0 + i) * plane + col;
+            if constexpr (NT) old[i] = z0 + i < box.nz ? __builtin_nontemporal_load(p) : 0.0f;
+            else old[i] = z0 + i < box.nz ? *p : 0.0f;
+        }
     }
 
     for (int k = 0; k < n_views; ++k) {
@@ -724,8 +734,12 @@ __global__ __launch_bounds__(kBlock, PADDED ? 1 : 8) void backproject_kernel(
         for (int i = 0; i < ZU; ++i) {
             if (z0 + i < box.nz) {
                 float* p = vol + (size_t)(z0 + i) * plane + col;
-                if constexpr (!PADDED) *p = old[i] + acc[i];  // the same sum as += (no other writer)
-                else *p += acc[i];
+                if constexpr (!PADDED) {  // the same sum as += (no other writer)
+                    if constexpr (NT) __builtin_nontemporal_store(old[i] + acc[i], p);
+                    else *p = old[i] + acc[i];
+                } else {
+                    *p += acc[i];
+                }
             }
         }
     }
@@ -1452,9 +1466,19 @@ hipError_t launch_zu(int zu, float* vol, const Box& box, const ViewConst* vc, in
         const long t = n_tiles(box.nx, box.ny, box.nz, z, TX);
         return dim3((unsigned)(xcd_order == 1 ? (t + kXcds - 1) / kXcds * kXcds : t));
     };
-#define BP_LAUNCH(Z)                                                                                         \
-    hipLaunchKernelGGL((backproject_kernel<Src, Z, PADDED, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, \
-                       cl.bits, cl.words, cl.kbase, xcd_order)
+    const bool nt = !PADDED && TX == 64 && (double)box.nx * (double)box.ny * (double)box.nz * 4.0 >= (double)(1u << 28);
+#define BP_LAUNCH(Z)                                                                                             \
+    do {                                                                                                         \
+        if constexpr (!PADDED && TX == 64) {                                                                     \
+            if (nt) {                                                                                            \
+                hipLaunchKernelGGL((backproject_kernel<Src, Z, PADDED, TX, true>), grid(Z), block, 0, s, vol, box, \
+                                   vc, n, src, cl.bits, cl.words, cl.kbase, xcd_order);                          \
+                break;                                                                                           \
+            }                                                                                                    \
+        }                                                                                                        \
+        hipLaunchKernelGGL((backproject_kernel<Src, Z, PADDED, TX>), grid(Z), block, 0, s, vol, box, vc, n, src, \
+                           cl.bits, cl.words, cl.kbase, xcd_order);                                              \
+    } while (0)
     switch (zu) {
     case 1: BP_LAUNCH(1); break;
     case 2: BP_LAUNCH(2); break;

@@ -305,6 +305,8 @@ class Bench:
         C = self.at.Candidate
         out = [C("fused", k, zu, tx, sp) for k in (32, 64, 128) for zu in (4, 8) for tx in (8, 16, 32)
                for sp in (-1, 0, 1, 2, 4)]
+        # wider passes, up to every view in one, in the shapes that lead at K = 64 and 128
+        out += [C("fused", k, 8, tx, sp) for k in (256, n) for tx in (16, 32) for sp in (-1, 0)]
         out += [C("fused", k, 8, 16, -1, True) for k in (32, 64)]
         return [c for c in out if c.views_per_pass <= n]
 
@@ -313,6 +315,7 @@ class Bench:
         out = [C("fused", k, 8, 16) for k in (1, 2, 4)]  # HBM-bound: the tile shape hardly matters
         out += [C("fused", k, zu, tx) for k in (8, 16) for zu in (4, 8) for tx in (16, 32)]
         out += [C("fused", k, 8, tx, sp) for k in (32, 64, 128) for tx in (16, 32) for sp in (-1, 0, 1, 2, 4)]
+        out += [C("fused", k, 8, tx, sp) for k in (256, 496) for tx in (16, 32) for sp in (-1, 0)]
         out += [C("fused", k, 8, 16, -1, True) for k in (64, 128)]
         return out
 

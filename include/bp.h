@@ -246,8 +246,8 @@ bp_status bp_set_tap_split(bp_ctx ctx, int direct_eighths);
  * direct_taps: 1 if the fused pass reads every tap through L1 (no LDS stage) -- set by
  * BP_OPT_DIRECT_TAPS, or chosen on boxes of 2e8 voxels or more for FP32 staging as records
  * (BP_OPT_STAGE_RECORDS) unless a tap split is set.  Pixel stages (the default) and compact
- * records keep the stage, with K = 64 for FP32 pixel stages of fewer than 2e8 voxels and
- * K = 128 otherwise. */
+ * records keep the stage: K = 64 for FP32 pixel stages of fewer than 2e8 voxels, every view in
+ * one pass (at most 512) for the other pixel stages, K = 128 for records. */
 bp_status bp_query_plan(bp_ctx ctx, int nx, int ny, int nz, int n_views,
                         bp_path *path, int *views_per_pass, int *z_unroll, int *tile_x, int *direct_taps);
 

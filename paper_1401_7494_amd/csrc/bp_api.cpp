@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -235,11 +236,14 @@ Plan plan_for(const bp_ctx_s* ctx, int nx, int ny, int nz, int n_views)
     if (p.k <= 0) {
         if (p.path == BP_PATH_FUSED_DIRECT) p.k = 64;
         else if (p.direct_taps) p.k = compact || voxels >= 2.0e8 ? 64 : 32;
-        // LDS-staged taps, measured at 496 views: K = 128 for 16-bit input (best at L = 512) and
-        // for large volumes (L = 1024: best of K = 1 .. 128); FP32 pixel stages below 2e8 voxels
-        // take K = 64, within 0.5% of K = 128 in time at L = 512 but with 20% less HBM traffic per
-        // update (the footprint bands of fewer views stay in L2)
-        else p.k = ctx->cfg.proj_dtype == BP_F32 && pixels && voxels < 2.0e8 ? 64 : 128;
+        // LDS-staged taps, measured at 496 views of 1248 x 960: pixel stages of 16-bit input and
+        // of large volumes take every view in one pass, up to 512 (against K = 128: BF16 at
+        // L = 512 +3.2%, FP32 and BF16 at L = 1024 +7.3% and +5.8%: the volume is read and written
+        // once); FP32 pixel stages below 2e8 voxels take K = 64, level in time with one pass and
+        // with K = 128 at L = 512 and with the least HBM traffic per update (the footprint bands
+        // of fewer views stay in L2); compact records K = 128
+        else if (pixels && (ctx->cfg.proj_dtype != BP_F32 || voxels >= 2.0e8)) p.k = std::min(n_views, 512);
+        else p.k = pixels ? 64 : 128;
     }
     if (p.path == BP_PATH_PLAIN) p.k = 1;
     if (p.k > n_views) p.k = n_views;

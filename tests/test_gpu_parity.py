@@ -242,13 +242,15 @@ def test_plan_reports_choices():
         ctx.set_tuning("fused_direct", 0, 0, 32)
         p = ctx.plan(128, 128, 128, 496)
         assert (p.path, p.views_per_pass, p.tile_x) == ("fused_direct", 64, 64)
-        # staged or direct taps: FP32 pixel stages at every size (K = 64 below 2e8 voxels, K = 128
-        # above); FP32 record stages at L = 512, direct reads on finer, larger grids
+        # staged or direct taps: FP32 pixel stages at every size (K = 64 below 2e8 voxels, every
+        # view in one pass above, up to 512); FP32 record stages at L = 512, direct reads on finer,
+        # larger grids
         ctx.set_tuning("auto", 0, 0, 0)
         p = ctx.plan(512, 512, 512, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, False)
         p = ctx.plan(1024, 1024, 1024, 496)
-        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 496, False)
+        assert ctx.plan(1024, 1024, 1024, 2000).views_per_pass == 512
         ctx.set_options(stage_records=True)
         p = ctx.plan(640, 640, 640, 496)
         assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 64, True)
@@ -260,8 +262,8 @@ def test_plan_reports_choices():
         assert (p.views_per_pass, p.direct_taps) == (32, True)
     with bp.Context(1248, 960, "bf16") as ctx:
         p = ctx.plan(1024, 1024, 1024, 496)
-        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 128, False)
-        assert ctx.plan(512, 512, 512, 496).views_per_pass == 128  # 16-bit stages: K = 128 at L = 512
+        assert (p.path, p.views_per_pass, p.direct_taps) == ("fused", 496, False)
+        assert ctx.plan(512, 512, 512, 496).views_per_pass == 496  # 16-bit stages: every view in one pass
         assert ctx.plan(320, 320, 320, 496).path == "fused_direct"  # 16-bit pairs: staged a little sooner
         assert ctx.plan(384, 384, 384, 496).path == "fused"
 
@@ -369,9 +371,9 @@ def test_parity_l512_sampled(dtype, compact, path):
 
 # Launches from the benchmark's search space at L = 512 (views per pass, z-unroll, tile width, tap
 # split, direct taps): the usual winner, a records split with wide tiles, the tuned split with
-# narrow tiles, and every tap read from the caller's images.
+# narrow tiles, every view in one pass, and every tap read from the caller's images.
 L512_TUNED_LAUNCHES = [(64, 8, 16, 0, False), (32, 4, 32, 4, False), (128, 8, 8, -1, False),
-                       (64, 8, 16, -1, True)]
+                       (496, 8, 32, 0, False), (64, 8, 16, -1, True)]
 
 
 def test_parity_l512_tuned_launches_sampled():

@@ -770,18 +770,20 @@ def test_stream_checkpoint_resume_is_bit_exact(small_inputs, k):
     assert np.array_equal(resumed, whole)
 
 
-def test_parity_l1024_sampled():
-    """L=1024 (voxel 0.25 mm, 4 GiB volume), 496 views streamed in passes: every 16th voxel
-    per axis (64^3 voxels spread over the volume) against the oracle."""
+@pytest.mark.parametrize("dtype,k", [("f32", 0), ("f32", 128), ("bf16", 0)])
+def test_parity_l1024_sampled(dtype, k):
+    """L=1024 (voxel 0.25 mm, 4 GiB volume), 496 views: every 16th voxel per axis (64^3 voxels
+    spread over the volume) against the oracle, in the library's launch (every view in one pass)
+    and in passes of 128 views; BF16 against the oracle on the same rounded values."""
     wl = synth.WORKLOADS["fdk_l1024_v496_f32"]
     v = wl.volume
-    proj = gc.full_projections(wl.phantom_seed)
+    proj = gc.full_projections(wl.phantom_seed).to(gc.TORCH_DTYPE[dtype])
     P32 = gc.product_matrices(wl.scanner)
-    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin)
+    got = gc.run_gpu(proj, P32, (v.L,) * 3, v.voxel_size, v.origin, dtype=dtype, k=k)
     xyz = strided_sample(v.L, 16, 7)
-    ref = oracle.backproject_points(proj.cpu().numpy(), P32.astype(np.float64), v.voxel_size, v.origin, xyz)
+    ref = oracle.backproject_points(proj.float().cpu().numpy(), P32.astype(np.float64), v.voxel_size, v.origin, xyz)
     err = gc.error_stats(got[xyz[:, 2], xyz[:, 1], xyz[:, 0]], ref)
-    print(f"\nL=1024 uniform sample: {err}")
+    print(f"\nL=1024 {dtype} K={k or 'library'} uniform sample: {err}")
     assert err["rel_l2"] <= gc.REL_L2_TOL, err
     assert err["max_abs_over_max"] <= gc.MAX_ABS_TOL, err
 
